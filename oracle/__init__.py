@@ -1,0 +1,192 @@
+"""CPU oracle for parallel flatPERM -- TEST INFRASTRUCTURE ONLY.
+
+The plain, slow, obviously-correct reference the GPU path is checked against
+(Campbell & Janse van Rensburg, "Parallel PERM": Sec. 1 Rosenbluth growth and
+eqns (1)-(4); Sec. 2 flatPERM, eqn (6); Sec. 3 / Fig. 1 Algorithms 1 and 2).
+Only tests/, the smoke check and the benchmark's CPU-baseline leg may import
+this package.  It shares no code with the HIP library and never takes an input
+produced by it.
+
+The arithmetic lives in C (pperm_oracle.c, saw_enum.c); this module only
+marshals numpy arrays into it.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+MODE_SHARED = 0        # Algorithm 2: pooled W
+MODE_INDEPENDENT = 1   # Algorithm 1: independent sequences
+MODE_ROSENBLUTH = 2    # plain Rosenbluth sampling (no prune / enrich)
+
+STATS_FIELDS = ("steps", "events", "enrich", "copies", "prunes", "traps",
+                "tours", "max_depth", "digest", "capped")
+STATS_DTYPE = np.dtype([(f, np.uint64) for f in STATS_FIELDS])
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("n_max", ctypes.c_int64), ("seed", ctypes.c_uint64),
+                ("stream", ctypes.c_uint32), ("pad", ctypes.c_uint32),
+                ("step_cap", ctypes.c_uint64)]
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype)) if a is not None else None
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        path = os.path.join(_HERE, "liboracle.so")
+        srcs = [os.path.join(_HERE, s) for s in _build.SOURCES]
+        if not os.path.exists(path) or any(os.path.getmtime(s) > os.path.getmtime(path) for s in srcs):
+            _build.build()
+        L = ctypes.CDLL(path)
+        u32p, u64p = ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint64)
+        dblp, i64p = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)
+        L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
+        L.orc_scale_exponent.argtypes = [ctypes.c_int, ctypes.c_int64]
+        L.orc_scale_exponent.restype = ctypes.c_int64
+        L.orc_weight_step.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int64]
+        L.orc_weight_step.restype = ctypes.c_double
+        L.orc_set_selftest.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.c_int64, ctypes.POINTER(ctypes.c_int32), ctypes.c_int64]
+        L.orc_set_selftest.restype = ctypes.c_int64
+        L.orc_stats_init.argtypes = [ctypes.c_void_p, ctypes.c_int64]
+        L.orc_run_epoch.argtypes = [ctypes.POINTER(_Params), ctypes.c_int64, dblp, u64p, u64p,
+                                    ctypes.c_uint32, dblp, u32p, u32p, ctypes.c_void_p,
+                                    i64p, ctypes.c_int64, ctypes.c_int]
+        L.orc_run_epoch.restype = ctypes.c_int
+        L.orc_merge.argtypes = [ctypes.POINTER(_Params), ctypes.c_int64, dblp, u32p, u32p,
+                                dblp, u64p, u64p]
+        L.orc_log_estimates.argtypes = [ctypes.c_int, ctypes.c_int64, dblp, ctypes.c_uint64, dblp]
+        L.orc_plain_recursive.argtypes = [ctypes.POINTER(_Params), ctypes.c_uint32, dblp, u32p]
+        L.orc_plain_recursive.restype = ctypes.c_int
+        L.orc_forced_enumerate.argtypes = [ctypes.c_int, ctypes.c_int64, u64p, u64p]
+        L.orc_forced_enumerate.restype = ctypes.c_int
+        L.saw_count.argtypes = [ctypes.c_int, ctypes.c_int, u64p]
+        L.saw_count.restype = ctypes.c_int
+        _LIB = L
+    return _LIB
+
+
+def philox4x32_10(ctr, key):
+    """One Philox4x32-10 block: ctr is 4 uint32 words, key is 2."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox4x32_10(_ptr(c, ctypes.c_uint32), _ptr(k, ctypes.c_uint32), _ptr(out, ctypes.c_uint32))
+    return out
+
+
+def scale_exponent(dim, n):
+    """E_n of the scaled-weight representation, W = w * 2^E_n."""
+    return int(lib().orc_scale_exponent(dim, n))
+
+
+def weight_step(dim, w, a, n):
+    return float(lib().orc_weight_step(dim, w, a, n))
+
+
+def saw_counts(dim, n_max):
+    """Exact c_0..c_n_max by brute-force enumeration."""
+    out = np.zeros(n_max + 1, dtype=np.uint64)
+    if lib().saw_count(dim, n_max, _ptr(out, ctypes.c_uint64)) != 0:
+        raise RuntimeError("saw_count failed")
+    return out
+
+
+def forced_enumerate(dim, n_max):
+    """Drive the oracle's scan and weight update over every chain.
+
+    Returns (count[n], bad) where count[n] is the number of chains of length n
+    and bad counts chains whose weight differs from the exact product of a_+."""
+    cnt = np.zeros(n_max + 1, dtype=np.uint64)
+    bad = np.zeros(1, dtype=np.uint64)
+    if lib().orc_forced_enumerate(dim, n_max, _ptr(cnt, ctypes.c_uint64), _ptr(bad, ctypes.c_uint64)) != 0:
+        raise RuntimeError("forced_enumerate failed")
+    return cnt, int(bad[0])
+
+
+def set_selftest(ops, xyz, max_items):
+    ops = np.ascontiguousarray(ops, dtype=np.int32)
+    xyz = np.ascontiguousarray(xyz, dtype=np.int32).reshape(-1)
+    out = np.zeros(int((ops == 2).sum()), dtype=np.int32)
+    c = lib().orc_set_selftest(_ptr(ops, ctypes.c_int32), _ptr(xyz, ctypes.c_int32), len(ops),
+                               _ptr(out, ctypes.c_int32), max_items)
+    return out, int(c)
+
+
+def plain_recursive(dim, n_max, seed, tours, mode=MODE_SHARED, stream=0):
+    """Plain flatPERM (one sequence, one epoch) in recursive form."""
+    p = _Params(dim, mode, n_max, seed, stream, 0, 0)
+    L = np.zeros(n_max + 1, dtype=np.float64)
+    H = np.zeros(n_max + 1, dtype=np.uint32)
+    if lib().orc_plain_recursive(ctypes.byref(p), tours, _ptr(L, ctypes.c_double), _ptr(H, ctypes.c_uint32)) != 0:
+        raise RuntimeError("plain_recursive failed")
+    return L, H
+
+
+class Oracle:
+    """Parallel flatPERM state and its epoch schedule (run / merge calls)."""
+
+    def __init__(self, dim, n_max, n_sequences, seed, mode=MODE_SHARED, stream=0,
+                 step_cap=0, threads=0):
+        self.params = _Params(dim, mode, n_max, seed & 0xFFFFFFFFFFFFFFFF, stream, 0, step_cap)
+        self.dim, self.n_max, self.N, self.mode = dim, n_max, n_sequences, mode
+        self.threads = threads
+        n1 = n_max + 1
+        gshape = (n_sequences, n1) if mode == MODE_INDEPENDENT else (n1,)
+        self.G = np.zeros(gshape, dtype=np.float64)
+        self.HG = np.zeros(gshape, dtype=np.uint64)
+        self.MG = np.zeros(n_sequences if mode == MODE_INDEPENDENT else 1, dtype=np.uint64)
+        self.t = np.zeros(n_sequences, dtype=np.uint64)
+        self.L = np.zeros((n_sequences, n1), dtype=np.float64)
+        self.H = np.zeros((n_sequences, n1), dtype=np.uint32)
+        self.m = np.zeros(n_sequences, dtype=np.uint32)
+        self.stats = np.zeros(n_sequences, dtype=STATS_DTYPE)
+        lib().orc_stats_init(self.stats.ctypes.data, n_sequences)
+
+    def run_tours(self, tours, ids=None):
+        """Every sequence (or only `ids`) runs `tours` more tours. Returns True if capped."""
+        idp, nid = None, 0
+        if ids is not None:
+            ids = np.ascontiguousarray(ids, dtype=np.int64)
+            idp, nid = _ptr(ids, ctypes.c_int64), len(ids)
+        rc = lib().orc_run_epoch(ctypes.byref(self.params), self.N, _ptr(self.G, ctypes.c_double),
+                                 _ptr(self.MG, ctypes.c_uint64), _ptr(self.t, ctypes.c_uint64),
+                                 tours, _ptr(self.L, ctypes.c_double), _ptr(self.H, ctypes.c_uint32),
+                                 _ptr(self.m, ctypes.c_uint32), self.stats.ctypes.data,
+                                 idp, nid, self.threads)
+        return bool(rc)
+
+    def merge_epoch(self):
+        lib().orc_merge(ctypes.byref(self.params), self.N, _ptr(self.L, ctypes.c_double),
+                        _ptr(self.H, ctypes.c_uint32), _ptr(self.m, ctypes.c_uint32),
+                        _ptr(self.G, ctypes.c_double), _ptr(self.HG, ctypes.c_uint64),
+                        _ptr(self.MG, ctypes.c_uint64))
+
+    def log_estimates(self):
+        """log c_n (shared mode: pooled; independent mode: per sequence rows)."""
+        n1 = self.n_max + 1
+        if self.mode == MODE_INDEPENDENT:
+            out = np.zeros((self.N, n1))
+            for s in range(self.N):
+                row = np.ascontiguousarray(self.G[s])
+                lib().orc_log_estimates(self.dim, self.n_max, _ptr(row, ctypes.c_double),
+                                        int(self.MG[s]), _ptr(out[s], ctypes.c_double))
+            return out
+        out = np.zeros(n1)
+        with np.errstate(divide="ignore"):
+            lib().orc_log_estimates(self.dim, self.n_max, _ptr(self.G, ctypes.c_double),
+                                    int(self.MG[0]), _ptr(out, ctypes.c_double))
+        return out
+
+    def walk_steps(self):
+        return int(self.stats["steps"].sum())

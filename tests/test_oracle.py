@@ -1,0 +1,300 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test names the passage it follows.  None of them compares the oracle with
+itself: the references are exact enumeration, the Rosenbluth counting theorem
+(Sec. 1, eqn (3)), exact small-n values, published Philox vectors, rocRAND's
+Philox, statistical unbiasedness of the sample average (eqn (4)) and the
+flat-histogram property of flatPERM (Sec. 2).
+"""
+import math
+import os
+import shutil
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _saw_golden():
+    out = {2: {}, 3: {}}
+    with open(os.path.join(GOLDEN, "saw_counts.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            d, n, c = line.split()
+            out[int(d)][int(n)] = int(c)
+    return out
+
+
+SAW = _saw_golden()
+
+
+def _exact(dim, n_max):
+    return np.array([SAW[dim][n] for n in range(n_max + 1)], dtype=np.float64)
+
+
+# --------------------------------------------------------------------------
+# Exact counts and the counting theorem (Sec. 1, eqns (1)-(3))
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dim,n_max", [(2, 20), (3, 13)])
+def test_brute_force_counts_match_literature(dim, n_max):
+    c = oracle.saw_counts(dim, n_max)
+    assert [int(x) for x in c] == [SAW[dim][n] for n in range(n_max + 1)]
+
+
+def test_small_counts_closed_forms():
+    # c_1 = 2d, c_2 = 2d(2d-1), c_3 = 2d(2d-1)^2; c_4 subtracts the 2d(2d-2)
+    # four-step walks that would close a unit square onto the origin.
+    for d in (2, 3):
+        c = oracle.saw_counts(d, 4)
+        q = 2 * d
+        assert int(c[1]) == q
+        assert int(c[2]) == q * (q - 1)
+        assert int(c[3]) == q * (q - 1) ** 2
+        assert int(c[4]) == q * (q - 1) ** 3 - q * (q - 2)
+
+
+@pytest.mark.parametrize("dim,n_max", [(2, 13), (3, 9)])
+def test_forced_choice_drive_counts_every_walk_once(dim, n_max):
+    # Every chain the sampler's scan admits is a SAW and every SAW is reached
+    # exactly once; W(S) equals prod a_+ exactly (eqn (2)), hence
+    # sum_S Pr(S) W(S) = #chains = c_n (eqn (3)).
+    cnt, bad = oracle.forced_enumerate(dim, n_max)
+    assert bad == 0
+    assert [int(x) for x in cnt] == [SAW[dim][n] for n in range(n_max + 1)]
+
+
+def test_scaled_exponent_tracks_growth_constant():
+    # E_n = floor(n log2 mu_d) in 32.32 fixed point; mu_d from Sec. 3.3.
+    for d, mu in ((2, 2.63815853035), (3, 4.684039931)):
+        for n in (0, 1, 2, 3, 10, 500, 1000, 2048, 32767):
+            e = oracle.scale_exponent(d, n)
+            assert e == math.floor(n * math.log2(mu)) or abs(n * math.log2(mu) - round(n * math.log2(mu))) < 1e-6
+            assert abs(e - n * math.log2(mu)) <= 1.0
+    assert oracle.weight_step(2, 1.0, 4, 0) == 4.0 / 2 ** oracle.scale_exponent(2, 1)
+
+
+# --------------------------------------------------------------------------
+# Philox4x32-10 (the counter-based generator of the RNG contract)
+# --------------------------------------------------------------------------
+
+def test_philox_known_answers():
+    with open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")) as f:
+        rows = [l.split() for l in f if l.strip() and not l.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(x, 16) for x in r]
+        got = oracle.philox4x32_10(v[0:4], v[4:6])
+        assert [int(x) for x in got] == v[6:10]
+
+
+_ROCRAND_PROG = r"""
+#include <rocrand/rocrand_philox4x32_10.h>
+#include <cstdio>
+int main() {
+  unsigned c0, c1, c2, c3, k0, k1;
+  while (scanf("%x %x %x %x %x %x", &c0, &c1, &c2, &c3, &k0, &k1) == 6) {
+    unsigned long long seed = (unsigned long long)k0 | ((unsigned long long)k1 << 32);
+    unsigned long long sub = (unsigned long long)c2 | ((unsigned long long)c3 << 32);
+    unsigned long long off = 4ull * ((unsigned long long)c0 | ((unsigned long long)c1 << 32));
+    rocrand_device::philox4x32_10_engine e(seed, sub, off);
+    unsigned a = e(), b = e(), c = e(), d = e();
+    printf("%08x %08x %08x %08x\n", a, b, c, d);
+  }
+  return 0;
+}
+"""
+
+
+@pytest.mark.skipif(shutil.which("hipcc") is None, reason="needs hipcc to build the rocRAND host check")
+def test_philox_matches_rocrand_host_engine():
+    # rocRAND's philox4x32_10 engine, executed on the host: seed -> key,
+    # subsequence -> counter words 2,3, offset/4 -> counter words 0,1.
+    rng = np.random.default_rng(7)
+    rows = []
+    for _ in range(200):
+        c = rng.integers(0, 2 ** 32, size=4, dtype=np.uint64)
+        c[1] %= 2 ** 30          # keeps 4 * offset inside 64 bits
+        k = rng.integers(0, 2 ** 32, size=2, dtype=np.uint64)
+        rows.append((c, k))
+    rows.append((np.array([5, 0, 17, 3], dtype=np.uint64), np.array([1, 0], dtype=np.uint64)))
+    with tempfile.TemporaryDirectory() as td:
+        src = os.path.join(td, "rr.cpp")
+        exe = os.path.join(td, "rr")
+        with open(src, "w") as f:
+            f.write(_ROCRAND_PROG)
+        subprocess.run(["hipcc", "-O1", src, "-o", exe], check=True, capture_output=True)
+        inp = "\n".join(" ".join("%08x" % int(x) for x in list(c) + list(k)) for c, k in rows)
+        out = subprocess.run([exe], input=inp, capture_output=True, text=True, check=True).stdout.split("\n")
+    for (c, k), line in zip(rows, out):
+        want = [int(x, 16) for x in line.split()]
+        got = oracle.philox4x32_10(c.astype(np.uint32), k.astype(np.uint32))
+        assert [int(x) for x in got] == want
+
+
+# --------------------------------------------------------------------------
+# The occupancy set behind a_+
+# --------------------------------------------------------------------------
+
+def test_occupancy_set_against_python_set():
+    rng = np.random.default_rng(3)
+    n = 20000
+    ops = rng.integers(0, 3, size=n)
+    pts = rng.integers(-6, 7, size=(n, 3))
+    got, count = oracle.set_selftest(ops, pts, max_items=2200)
+    ref, want = set(), []
+    for op, p in zip(ops, map(tuple, pts)):
+        if op == 0:
+            ref.add(p)
+        elif op == 1:
+            ref.discard(p)
+        else:
+            want.append(int(p in ref))
+    assert got.tolist() == want
+    assert count == len(ref)
+
+
+# --------------------------------------------------------------------------
+# Exact consequences of the construction (Sec. 1, Sec. 2)
+# --------------------------------------------------------------------------
+
+def _cn_hat(o):
+    n = np.arange(o.n_max + 1)
+    e = np.array([oracle.scale_exponent(o.dim, int(k)) for k in n], dtype=np.float64)
+    return o.G / float(o.MG[0]) * np.exp2(e)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("N,T,epochs,seed", [(1, 500, 1, 1), (7, 20, 3, 5), (16, 3, 4, 11)])
+def test_lengths_up_to_three_are_exact(dim, N, T, epochs, seed):
+    # For n <= 3 every walk has the same weight 2d(2d-1)^(n-1) (no endpoint can
+    # touch an earlier site before n = 4), so r = 1 exactly and c_1..c_3 come out
+    # exact for every seed, sequence count and epoch schedule.
+    o = oracle.Oracle(dim, 12, N, seed, step_cap=10 ** 6)
+    for _ in range(epochs):
+        assert o.run_tours(T) is False
+        o.merge_epoch()
+    c = _cn_hat(o)
+    q = 2 * dim
+    assert c[0] == 1.0
+    assert c[1] == q and c[2] == q * (q - 1) and c[3] == q * (q - 1) ** 2
+    assert int(o.MG[0]) == N * T * epochs
+    assert int(o.HG[0]) == N * T * epochs
+
+
+@pytest.mark.parametrize("dim,seed", [(2, 1), (2, 9), (3, 4)])
+def test_first_tour_is_a_rosenbluth_walk(dim, seed):
+    # In the first tour of a lone sequence every running average is the walk's
+    # own weight (eqn (6) with the weight included), so r = 1, no copies and no
+    # pruning: the tour is exactly the Rosenbluth walk drawn from the same numbers.
+    a = oracle.Oracle(dim, 60, 1, seed, step_cap=10000)
+    assert a.run_tours(1) is False
+    b = oracle.Oracle(dim, 60, 1, seed, mode=oracle.MODE_ROSENBLUTH)
+    b.run_tours(1)
+    assert np.array_equal(a.L, b.L) and np.array_equal(a.H, b.H)
+    assert a.stats["enrich"][0] == 0 and a.stats["prunes"][0] == 0
+    assert a.stats["digest"][0] == b.stats["digest"][0]
+
+
+@pytest.mark.parametrize("dim,n_max,seed,tours", [(2, 20, 1, 3000), (2, 40, 2, 2000), (3, 30, 3, 2000)])
+def test_iterative_matches_recursive_description(dim, n_max, seed, tours):
+    o = oracle.Oracle(dim, n_max, 1, seed)
+    o.run_tours(tours)
+    L, H = oracle.plain_recursive(dim, n_max, seed, tours)
+    assert np.array_equal(o.L[0], L)
+    assert np.array_equal(o.H[0], H)
+
+
+def test_thread_count_does_not_change_results():
+    runs = []
+    for th in (1, 3, 8):
+        o = oracle.Oracle(3, 40, 19, 77, threads=th)
+        for _ in range(2):
+            o.run_tours(5)
+            o.merge_epoch()
+        runs.append((o.G.copy(), o.HG.copy(), o.stats.copy()))
+    for g, h, s in runs[1:]:
+        assert np.array_equal(g, runs[0][0]) and np.array_equal(h, runs[0][1])
+        assert np.array_equal(s, runs[0][2])
+
+
+def test_merge_is_the_aligned_pairwise_tree():
+    # Values chosen so that the summation order is visible in the rounding.
+    o = oracle.Oracle(2, 2, 5, 1)
+    big = 2.0 ** 53
+    o.L[:, 1] = [big, 1.0, 1.0, 1.0, 1.0]
+    o.m[:] = 1
+    o.merge_epoch()
+    # tree over 8 leaves: (((b+1)+(1+1)) + ((1+0)+(0+0)))
+    want = ((big + 1.0) + (1.0 + 1.0)) + ((1.0 + 0.0) + (0.0 + 0.0))
+    assert o.G[1] == want
+    assert o.G[1] != (((big + 1.0) + 1.0) + 1.0) + 1.0
+    assert int(o.MG[0]) == 5
+    assert not o.L.any() and not o.H.any() and not o.m.any()
+
+
+def test_step_cap_stops_a_sequence():
+    o = oracle.Oracle(2, 100, 2, 3, step_cap=50)
+    assert o.run_tours(100) is True
+    assert (o.stats["capped"] == 1).all()
+    assert (o.stats["steps"] == 50).all()
+
+
+# --------------------------------------------------------------------------
+# Statistical pins: <W_n>_M is an unbiased estimate of c_n (eqns (3), (4))
+# --------------------------------------------------------------------------
+
+def _replicas(dim, n_max, N, T, epochs, seeds, mode=oracle.MODE_SHARED):
+    est = []
+    for sd in seeds:
+        o = oracle.Oracle(dim, n_max, N, sd, mode=mode)
+        for _ in range(epochs):
+            o.run_tours(T)
+            o.merge_epoch()
+        if mode == oracle.MODE_INDEPENDENT:
+            n = np.arange(n_max + 1)
+            e = np.exp2([oracle.scale_exponent(dim, int(k)) for k in n])
+            est.append(((o.G / o.MG[:, None].astype(float)) * e).mean(axis=0))
+        else:
+            est.append(_cn_hat(o))
+    return np.array(est)
+
+
+@pytest.mark.parametrize("case", [
+    dict(dim=2, n_max=14, N=1, T=2000, epochs=1, mode=oracle.MODE_SHARED),
+    dict(dim=3, n_max=10, N=1, T=2000, epochs=1, mode=oracle.MODE_SHARED),
+    dict(dim=2, n_max=14, N=8, T=25, epochs=10, mode=oracle.MODE_SHARED),
+    dict(dim=3, n_max=10, N=8, T=25, epochs=10, mode=oracle.MODE_SHARED),
+    dict(dim=2, n_max=14, N=4, T=50, epochs=10, mode=oracle.MODE_INDEPENDENT),
+    dict(dim=2, n_max=14, N=1, T=4000, epochs=1, mode=oracle.MODE_ROSENBLUTH),
+])
+def test_sample_average_is_unbiased(case):
+    seeds = range(1000, 1096)
+    est = _replicas(case["dim"], case["n_max"], case["N"], case["T"], case["epochs"], seeds, case["mode"])
+    exact = _exact(case["dim"], case["n_max"])
+    mean = est.mean(axis=0)
+    se = est.std(axis=0, ddof=1) / math.sqrt(len(seeds))
+    z = np.where(se > 0, (mean - exact) / np.where(se > 0, se, 1.0), 0.0)
+    assert np.all(np.abs(z) < 4.5), z
+    # and the pooled estimate is close in relative terms
+    assert np.all(np.abs(mean / exact - 1.0) < 0.02)
+
+
+def test_plain_flatperm_c1_budget():
+    # Plain flatPERM, one sequence, n_max = 20, 10^5 tours, seed 1: every
+    # estimate within 1% of the exact count, n <= 3 exact, histogram flat.
+    o = oracle.Oracle(2, 20, 1, 1)
+    o.run_tours(100000)
+    o.merge_epoch()
+    c = _cn_hat(o)
+    exact = _exact(2, 20)
+    assert np.all(np.abs(c / exact - 1.0) < 1e-2)
+    assert np.array_equal(c[:4], exact[:4])
+    flat = o.HG / float(o.MG[0])
+    assert flat.min() > 0.9 and flat.max() < 1.1
