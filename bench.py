@@ -1,0 +1,179 @@
+#!/usr/bin/env python3
+"""Benchmark: walk-steps/s of parallel flatPERM on one MI355X.
+
+One benchmark step is one whole job of the parallel square-lattice workload:
+4096 interacting flatPERM sequences (Algorithm 2), n_max = 500, a merge every
+64 tours, 38 epochs = 9,961,472 tours, followed by the read-out of log c_n.
+Every step runs a fresh job with its own seed; the workspaces are allocated
+and initialised before the timed region, so the timed region holds exactly the
+hot path: growth with a_+ scans, weight updates, prune/enrich, accumulation,
+merges and the estimate read-out.
+
+Printed: one JSON line with the metric, a roofline object for the dominant
+kernel (the growth kernel, timed with HIP events on its stream) and the CPU
+oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads  # noqa: E402
+
+# Algorithmic work per walk-step of the growth kernel (32-bit VALU lane operations
+# of the minimal single-walk step: Philox4x32-10 block 100, occupancy scan
+# 7 per neighbour query with 2d - 1 queries, control 15, growth 15, record 6).
+ALG_OPS_PER_STEP = {2: 100 + 7 * 3 + 15 + 15 + 6, 3: 100 + 7 * 5 + 15 + 15 + 6}
+# MI355X 32-bit VALU peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one lane-op per lane per clock).
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+WORKLOADS = {
+    "parallel2d": workloads.PARALLEL_2D,
+    "parallel3d": workloads.PARALLEL_3D,
+    "plain2d": workloads.PLAIN_2D,
+}
+
+
+def describe(p):
+    sched = p.schedule()
+    return (f"parallel flatPERM (Algorithm 2), Z^{p.dim}, N={p.n_sequences} sequences, "
+            f"n_max={p.n_max}, {len(sched)} epochs: warm-up {sched[:len(sched) - p.epochs + 1]} "
+            f"then {p.epochs - 1} x {p.tours_per_epoch} tours/sequence ({p.total_tours} tours)")
+
+
+def cpu_baseline(p, budget_s=15.0):
+    """The oracle, as it stands, on a bounded sample of the same job: its epochs
+    in order (run + merge, all sequences, all host cores) until the time budget
+    is spent, stopping at an epoch boundary."""
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
+    o = oracle.Oracle(p.dim, p.n_max, p.n_sequences, p.seed, threads=threads)
+    done, t0 = 0, time.perf_counter()
+    for T in p.schedule():
+        o.run_tours(T)
+        o.merge_epoch()
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    steps = o.walk_steps()
+    return {"value": steps / dt, "unit": "walk-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"the first {done} epochs of the same job ({steps} walk-steps, "
+                      f"{o.N * int(o.MG[0]) // max(o.N, 1)} tours) in {dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="parallel2d", choices=sorted(WORKLOADS))
+    ap.add_argument("--epochs", type=int, default=0, help="override the epoch count (profiling)")
+    ap.add_argument("--walks-per-wave", type=int, default=0)
+    ap.add_argument("--hash-slots", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding "
+              "of the method is described in the design notes, not run.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2002_03000_amd import ParallelFlatPERM
+
+    p = WORKLOADS[args.workload]
+    if args.epochs:
+        p = p.scaled(epochs=args.epochs)
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+
+    def make(seed):
+        return ParallelFlatPERM(p.dim, p.n_max, p.n_sequences, seed, mode=p.mode,
+                                walks_per_wave=args.walks_per_wave, hash_slots=args.hash_slots)
+
+    sched = p.schedule()
+
+    def job(g, ev=None):
+        for T in sched:
+            if ev is not None:
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                g.run_tours(T)
+                b.record(stream)
+                ev.append((a, b))
+            else:
+                g.run_tours(T)
+            g.merge_epoch()
+        return g.estimates()
+
+    # warmup (its own seeds)
+    for i in range(args.warmup):
+        g = make(p.seed + 1000 + i)
+        job(g)
+        g.close()
+        del g
+    torch.cuda.synchronize()
+
+    ctxs = [make(p.seed + i) for i in range(args.steps)]
+    torch.cuda.synchronize()
+    events = []
+    results = []
+    t0 = time.perf_counter()
+    for g in ctxs:
+        results.append(job(g, events))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    steps_total = 0
+    for g in ctxs:
+        steps_total += g.stats()["steps"]
+    run_ms = sum(a.elapsed_time(b) for a, b in events)
+    launches = len(events)
+    shape = ctxs[0].launch_shape()
+
+    value = steps_total / elapsed
+    kernel_rate = steps_total / (run_ms / 1e3)
+    ops = ALG_OPS_PER_STEP[p.dim]
+    achieved = kernel_rate * ops / 1e12
+    est_top = np.array([r[0][p.n_max] for r in results])
+    rel_err = float(np.std(np.exp(est_top - est_top.mean()), ddof=1)) if len(results) > 1 else None
+
+    line = {
+        "metric": "walk-steps/s (parallel flatPERM, 1 GPU)",
+        "value": value,
+        "unit": "walk-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (walks grown from parameters; seeds per job)",
+        "config": {"workload": describe(p), "dim": p.dim, "n_max": p.n_max,
+                   "n_sequences": p.n_sequences, "tours_per_epoch": p.tours_per_epoch,
+                   "epochs": len(sched), "schedule": sched[:len(sched) - p.epochs + 2],
+                   "walk_steps_per_job": steps_total // args.steps,
+                   "launch": shape},
+        "cn_rel_err_nmax": rel_err,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
+                     "frac": achieved / ALU_PEAK_TOPS, "traffic": None,
+                     "kernel": "run_kernel", "avg_launch_ms": run_ms / launches,
+                     "alg_ops_per_step": ops},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(p)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

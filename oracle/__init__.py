@@ -27,13 +27,19 @@ MODE_ROSENBLUTH = 2    # plain Rosenbluth sampling (no prune / enrich)
 STATS_FIELDS = ("steps", "events", "enrich", "copies", "prunes", "traps",
                 "tours", "max_depth", "digest", "capped")
 STATS_DTYPE = np.dtype([(f, np.uint64) for f in STATS_FIELDS])
+# extended-range number m * 2^e (m in [0.5, 1), or m = 0 and e = 0)
+XF_DTYPE = np.dtype([("m", np.float64), ("e", np.int32), ("pad", np.uint32)])
+
+
+class XF_C(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_double), ("e", ctypes.c_int32), ("pad", ctypes.c_uint32)]
 
 
 class _Params(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("n_max", ctypes.c_int64), ("seed", ctypes.c_uint64),
                 ("stream", ctypes.c_uint32), ("pad", ctypes.c_uint32),
-                ("step_cap", ctypes.c_uint64)]
+                ("step_cap", ctypes.c_uint64), ("n_pool", ctypes.c_uint64)]
 
 
 def _ptr(a, ctype):
@@ -51,22 +57,24 @@ def lib():
         u32p, u64p = ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint64)
         dblp, i64p = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)
         L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
-        L.orc_scale_exponent.argtypes = [ctypes.c_int, ctypes.c_int64]
-        L.orc_scale_exponent.restype = ctypes.c_int64
-        L.orc_weight_step.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int64]
-        L.orc_weight_step.restype = ctypes.c_double
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        L.orc_xf_apply.argtypes = [ctypes.c_int, dblp, i32p, dblp, i32p, dblp, ctypes.c_int64, dblp, i32p]
+        L.orc_xf_normalize.argtypes = [dblp, ctypes.c_int64, dblp, i32p]
+        L.orc_xf_ratio.argtypes = [XF_C, XF_C]
+        L.orc_xf_ratio.restype = ctypes.c_double
         L.orc_set_selftest.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                        ctypes.c_int64, ctypes.POINTER(ctypes.c_int32), ctypes.c_int64]
         L.orc_set_selftest.restype = ctypes.c_int64
         L.orc_stats_init.argtypes = [ctypes.c_void_p, ctypes.c_int64]
-        L.orc_run_epoch.argtypes = [ctypes.POINTER(_Params), ctypes.c_int64, dblp, u64p, u64p,
-                                    ctypes.c_uint32, dblp, u32p, u32p, ctypes.c_void_p,
+        vp = ctypes.c_void_p
+        L.orc_run_epoch.argtypes = [ctypes.POINTER(_Params), ctypes.c_int64, vp, u64p, u64p,
+                                    ctypes.c_uint32, vp, u32p, u32p, vp,
                                     i64p, ctypes.c_int64, ctypes.c_int]
         L.orc_run_epoch.restype = ctypes.c_int
-        L.orc_merge.argtypes = [ctypes.POINTER(_Params), ctypes.c_int64, dblp, u32p, u32p,
-                                dblp, u64p, u64p]
-        L.orc_log_estimates.argtypes = [ctypes.c_int, ctypes.c_int64, dblp, ctypes.c_uint64, dblp]
-        L.orc_plain_recursive.argtypes = [ctypes.POINTER(_Params), ctypes.c_uint32, dblp, u32p]
+        L.orc_merge.argtypes = [ctypes.POINTER(_Params), ctypes.c_int64, vp, u32p, u32p,
+                                vp, u64p, u64p]
+        L.orc_log_estimates.argtypes = [ctypes.c_int64, vp, ctypes.c_uint64, dblp]
+        L.orc_plain_recursive.argtypes = [ctypes.POINTER(_Params), ctypes.c_uint32, vp, u32p]
         L.orc_plain_recursive.restype = ctypes.c_int
         L.orc_forced_enumerate.argtypes = [ctypes.c_int, ctypes.c_int64, u64p, u64p]
         L.orc_forced_enumerate.restype = ctypes.c_int
@@ -85,13 +93,37 @@ def philox4x32_10(ctr, key):
     return out
 
 
-def scale_exponent(dim, n):
-    """E_n of the scaled-weight representation, W = w * 2^E_n."""
-    return int(lib().orc_scale_exponent(dim, n))
+def xf_from_float(x):
+    """Normalise doubles into extended-range numbers (m, e)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    m = np.zeros(len(x)); e = np.zeros(len(x), dtype=np.int32)
+    lib().orc_xf_normalize(_ptr(x, ctypes.c_double), len(x), _ptr(m, ctypes.c_double), _ptr(e, ctypes.c_int32))
+    return m, e
 
 
-def weight_step(dim, w, a, n):
-    return float(lib().orc_weight_step(dim, w, a, n))
+def xf_apply(op, am, ae, bm=None, be=None, k=None):
+    """Elementwise extended-range add (op 'add'), multiply or divide by k ('mul', 'div')."""
+    n = len(am)
+    am = np.ascontiguousarray(am, dtype=np.float64); ae = np.ascontiguousarray(ae, dtype=np.int32)
+    bm = np.ascontiguousarray(bm if bm is not None else np.zeros(n), dtype=np.float64)
+    be = np.ascontiguousarray(be if be is not None else np.zeros(n), dtype=np.int32)
+    k = np.ascontiguousarray(k if k is not None else np.ones(n), dtype=np.float64)
+    om = np.zeros(n); oe = np.zeros(n, dtype=np.int32)
+    code = {"add": 0, "mul": 1, "div": 2}[op]
+    lib().orc_xf_apply(code, _ptr(am, ctypes.c_double), _ptr(ae, ctypes.c_int32), _ptr(bm, ctypes.c_double),
+                       _ptr(be, ctypes.c_int32), _ptr(k, ctypes.c_double), n,
+                       _ptr(om, ctypes.c_double), _ptr(oe, ctypes.c_int32))
+    return om, oe
+
+
+def xf_ratio(am, ae, bm, be):
+    return float(lib().orc_xf_ratio(XF_C(am, ae, 0), XF_C(bm, be, 0)))
+
+
+def xf_log(a):
+    """Natural log of extended-range values (structured XF_DTYPE array)."""
+    with np.errstate(divide="ignore"):
+        return np.log(a["m"]) + a["e"].astype(np.float64) * np.log(2.0)
 
 
 def saw_counts(dim, n_max):
@@ -125,10 +157,10 @@ def set_selftest(ops, xyz, max_items):
 
 def plain_recursive(dim, n_max, seed, tours, mode=MODE_SHARED, stream=0):
     """Plain flatPERM (one sequence, one epoch) in recursive form."""
-    p = _Params(dim, mode, n_max, seed, stream, 0, 0)
-    L = np.zeros(n_max + 1, dtype=np.float64)
+    p = _Params(dim, mode, n_max, seed, stream, 0, 0, 1)
+    L = np.zeros(n_max + 1, dtype=XF_DTYPE)
     H = np.zeros(n_max + 1, dtype=np.uint32)
-    if lib().orc_plain_recursive(ctypes.byref(p), tours, _ptr(L, ctypes.c_double), _ptr(H, ctypes.c_uint32)) != 0:
+    if lib().orc_plain_recursive(ctypes.byref(p), tours, L.ctypes.data, _ptr(H, ctypes.c_uint32)) != 0:
         raise RuntimeError("plain_recursive failed")
     return L, H
 
@@ -138,16 +170,17 @@ class Oracle:
 
     def __init__(self, dim, n_max, n_sequences, seed, mode=MODE_SHARED, stream=0,
                  step_cap=0, threads=0):
-        self.params = _Params(dim, mode, n_max, seed & 0xFFFFFFFFFFFFFFFF, stream, 0, step_cap)
+        self.params = _Params(dim, mode, n_max, seed & 0xFFFFFFFFFFFFFFFF, stream, 0, step_cap,
+                              n_sequences)
         self.dim, self.n_max, self.N, self.mode = dim, n_max, n_sequences, mode
         self.threads = threads
         n1 = n_max + 1
         gshape = (n_sequences, n1) if mode == MODE_INDEPENDENT else (n1,)
-        self.G = np.zeros(gshape, dtype=np.float64)
+        self.G = np.zeros(gshape, dtype=XF_DTYPE)
         self.HG = np.zeros(gshape, dtype=np.uint64)
         self.MG = np.zeros(n_sequences if mode == MODE_INDEPENDENT else 1, dtype=np.uint64)
         self.t = np.zeros(n_sequences, dtype=np.uint64)
-        self.L = np.zeros((n_sequences, n1), dtype=np.float64)
+        self.L = np.zeros((n_sequences, n1), dtype=XF_DTYPE)
         self.H = np.zeros((n_sequences, n1), dtype=np.uint32)
         self.m = np.zeros(n_sequences, dtype=np.uint32)
         self.stats = np.zeros(n_sequences, dtype=STATS_DTYPE)
@@ -159,33 +192,29 @@ class Oracle:
         if ids is not None:
             ids = np.ascontiguousarray(ids, dtype=np.int64)
             idp, nid = _ptr(ids, ctypes.c_int64), len(ids)
-        rc = lib().orc_run_epoch(ctypes.byref(self.params), self.N, _ptr(self.G, ctypes.c_double),
+        rc = lib().orc_run_epoch(ctypes.byref(self.params), self.N, self.G.ctypes.data,
                                  _ptr(self.MG, ctypes.c_uint64), _ptr(self.t, ctypes.c_uint64),
-                                 tours, _ptr(self.L, ctypes.c_double), _ptr(self.H, ctypes.c_uint32),
+                                 tours, self.L.ctypes.data, _ptr(self.H, ctypes.c_uint32),
                                  _ptr(self.m, ctypes.c_uint32), self.stats.ctypes.data,
                                  idp, nid, self.threads)
         return bool(rc)
 
     def merge_epoch(self):
-        lib().orc_merge(ctypes.byref(self.params), self.N, _ptr(self.L, ctypes.c_double),
+        lib().orc_merge(ctypes.byref(self.params), self.N, self.L.ctypes.data,
                         _ptr(self.H, ctypes.c_uint32), _ptr(self.m, ctypes.c_uint32),
-                        _ptr(self.G, ctypes.c_double), _ptr(self.HG, ctypes.c_uint64),
+                        self.G.ctypes.data, _ptr(self.HG, ctypes.c_uint64),
                         _ptr(self.MG, ctypes.c_uint64))
 
     def log_estimates(self):
-        """log c_n (shared mode: pooled; independent mode: per sequence rows)."""
-        n1 = self.n_max + 1
+        """log c_n: the pooled average (shared mode) or, in independent mode, the
+        log of the mean over sequences of each sequence's average (eqn (7))."""
         if self.mode == MODE_INDEPENDENT:
-            out = np.zeros((self.N, n1))
-            for s in range(self.N):
-                row = np.ascontiguousarray(self.G[s])
-                lib().orc_log_estimates(self.dim, self.n_max, _ptr(row, ctypes.c_double),
-                                        int(self.MG[s]), _ptr(out[s], ctypes.c_double))
-            return out
-        out = np.zeros(n1)
-        with np.errstate(divide="ignore"):
-            lib().orc_log_estimates(self.dim, self.n_max, _ptr(self.G, ctypes.c_double),
-                                    int(self.MG[0]), _ptr(out, ctypes.c_double))
+            per = xf_log(self.G) - np.log(self.MG.astype(np.float64))[:, None]
+            top = per.max(axis=0)
+            with np.errstate(invalid="ignore"):
+                return top + np.log(np.exp(per - top).sum(axis=0)) - np.log(self.N)
+        out = np.zeros(self.n_max + 1)
+        lib().orc_log_estimates(self.n_max, self.G.ctypes.data, int(self.MG[0]), _ptr(out, ctypes.c_double))
         return out
 
     def walk_steps(self):

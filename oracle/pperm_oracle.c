@@ -26,10 +26,15 @@
  * design notes of the repository):
  *   R1  sharing is epoch-synchronous: inside an epoch a sequence sees the pooled
  *       sums frozen at the last merge plus its own sums of the current epoch;
- *   R2  est = (G_n + L_n) / (M_G + m), own current weight and own current tour
- *       included;
+ *   R2  inside an epoch a sequence extrapolates the pool's progress from its own:
+ *       est = (G_n + N * L_n) / (M_G + N * m) in Algorithm 2 (N sequences, L_n
+ *       and m its own sums and tours of the epoch, its current weight and tour
+ *       included), est = (G_n + L_n) / (M_G + m) with its own G, M_G in
+ *       Algorithm 1; N = 1 is plain flatPERM's running average;
  *   R3  copies are grown depth first, copy 1 first, the rest from a LIFO stack;
- *   R4  a pruned-but-surviving walk takes weight est (= W / r mathematically);
+ *   R4  r = W / est is evaluated as (W * M') / S for est = S / M' (S the weight
+ *       sum, M' the tour count of R2), and a pruned-but-surviving walk takes
+ *       weight est = S / M' (= W / r mathematically);
  *   R5  no control at n = 0, at n = n_max, or for a trapped walk; a resumed copy
  *       grows without a new control decision (the copies share one record);
  *   R6  randomness: Philox4x32-10, key = seed, counter = (k_lo, k_hi, t_lo, s),
@@ -37,9 +42,10 @@
  *   R7  j-th free neighbour with j = (B0 * a_+) >> 32, neighbours in the order
  *       +x, -x, +y, -y, +z, -z; u = ((B1 >> 5) * 2^26 + (B2 >> 6)) * 2^-53;
  *       c = floor r iff (r not integral and u < (floor r + 1) - r); survive iff u < r;
- *   R8  weights are held in scaled FP64 units, W = w * 2^E_n with the integer
- *       exponent E_n = floor(n * Q_d / 2^32), Q_d = round(log2(mu_d) * 2^32) from
- *       the literature growth constants quoted in Sec. 3.3 (eqn (12));
+ *   R8  weights and weight sums are extended-range numbers m * 2^e (FP64
+ *       mantissa, int32 exponent) whose operations are correctly rounded; the
+ *       weights of the first walks into new lengths shrink by a factor of about
+ *       m per length and leave the FP64 range long before n = 500;
  *   R9  the pooled sums are merged with an aligned pairwise tree over sequences,
  *       padded with +0.0 to a power of two.
  *
@@ -86,25 +92,71 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
 }
 
 /* ------------------------------------------------------------------------ */
-/* Scaled weights (reading R8).                                              */
+/* Extended-range weights (reading R8).  A weight is x = m * 2^e with the   */
+/* FP64 mantissa m in [0.5, 1) (m = 0, e = 0 for zero) and an int32          */
+/* exponent e.  Each operation below is the correctly rounded IEEE result of */
+/* the exact operation on the represented values, renormalised exactly:      */
+/* nothing can underflow or overflow, and no transcendental function is      */
+/* ever used on the decision path.                                           */
 /* ------------------------------------------------------------------------ */
-/* round(log2(2.63815853035) * 2^32) and round(log2(4.684039931) * 2^32):     */
-/* the literature growth constants for the square and cubic lattices.        */
-#define ORC_Q2 6010940994ull
-#define ORC_Q3 9568127888ull
+typedef struct { double m; int32_t e; uint32_t pad; } orc_xf;
 
-int64_t orc_scale_exponent(int dim, int64_t n)
+static orc_xf orc_xf_norm(double x, int32_t e)
 {
-    uint64_t q = (dim == 2) ? ORC_Q2 : ORC_Q3;
-    return (int64_t)(((uint64_t)n * q) >> 32);
+    orc_xf r;
+    int k = 0;
+    double m = frexp(x, &k);
+    if (m == 0.0) { r.m = 0.0; r.e = 0; r.pad = 0; return r; }
+    r.m = m; r.e = e + k; r.pad = 0;
+    return r;
 }
 
-/* One Rosenbluth weight update, eqn (2): W_{n+1} = W_n * a_+(w_n), written in
- * scaled units: w_{n+1} = (w_n * a) * 2^(E_n - E_{n+1}). */
-double orc_weight_step(int dim, double w, int a, int64_t n)
+static orc_xf orc_xf_from_double(double x) { return orc_xf_norm(x, 0); }
+
+/* a + b: the operand with the larger exponent keeps its scale and the other is
+ * shifted onto it (an exact scaling by a power of two); beyond 63 binades the
+ * smaller operand cannot change the rounded sum and is dropped. */
+orc_xf orc_xf_add(orc_xf a, orc_xf b)
 {
-    int64_t de = orc_scale_exponent(dim, n + 1) - orc_scale_exponent(dim, n);
-    return ldexp(w * (double)a, (int)(-de));
+    if (a.m == 0.0) return b;
+    if (b.m == 0.0) return a;
+    if (a.e < b.e) { orc_xf t = a; a = b; b = t; }
+    int64_t d = (int64_t)a.e - (int64_t)b.e;
+    if (d > 63) return a;
+    return orc_xf_norm(a.m + ldexp(b.m, (int)(-d)), a.e);
+}
+
+/* a * k and a / k for a positive integer-valued double k. */
+orc_xf orc_xf_mul(orc_xf a, double k) { return orc_xf_norm(a.m * k, a.e); }
+orc_xf orc_xf_div(orc_xf a, double k) { return orc_xf_norm(a.m / k, a.e); }
+
+/* a / b as an ordinary double (b != 0): ldexp(a.m / b.m, a.e - b.e), with the
+ * exponent difference clamped to [-1000, 1000] (0 below, 2^1000 above). */
+double orc_xf_ratio(orc_xf a, orc_xf b)
+{
+    if (a.m == 0.0) return 0.0;
+    int64_t d = (int64_t)a.e - (int64_t)b.e;
+    if (d < -1000) return 0.0;
+    if (d > 1000) return ldexp(1.0, 1000);
+    return ldexp(a.m / b.m, (int)d);
+}
+
+/* Test hooks: the operations on arrays (op 0 add, 1 mul, 2 div). */
+void orc_xf_apply(int op, const double* am, const int32_t* ae, const double* bm, const int32_t* be,
+                  const double* k, int64_t n, double* om, int32_t* oe)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        orc_xf a = { am[i], ae[i], 0 }, r;
+        if (op == 0) { orc_xf b = { bm[i], be[i], 0 }; r = orc_xf_add(a, b); }
+        else if (op == 1) r = orc_xf_mul(a, k[i]);
+        else r = orc_xf_div(a, k[i]);
+        om[i] = r.m; oe[i] = r.e;
+    }
+}
+
+void orc_xf_normalize(const double* x, int64_t n, double* om, int32_t* oe)
+{
+    for (int64_t i = 0; i < n; ++i) { orc_xf r = orc_xf_from_double(x[i]); om[i] = r.m; oe[i] = r.e; }
 }
 
 /* ------------------------------------------------------------------------ */
@@ -302,6 +354,7 @@ typedef struct {
     uint32_t stream;        /* xored into the key's high word (problem id) */
     uint32_t pad;
     uint64_t step_cap;      /* growth steps per sequence per call; 0 = none */
+    uint64_t n_pool;        /* N of reading R2 (number of pooled sequences) */
 } orc_params;
 
 /* Per-sequence counters, cumulative over the whole run. */
@@ -351,15 +404,18 @@ static double orc_uniform53(const uint32_t B[4])
 /*   t     : this sequence's global tour counter                             */
 /* Returns 0, or 1 if the step cap stopped the sequence.                    */
 /* ------------------------------------------------------------------------ */
-typedef struct { int64_t n; uint64_t remaining; double w; } orc_entry;
+typedef struct { int64_t n; uint64_t remaining; orc_xf w; } orc_entry;
 
-int orc_run_sequence(const orc_params* P, const double* G, uint64_t MG,
+int orc_run_sequence(const orc_params* P, const orc_xf* G, uint64_t MG,
                      uint32_t s, uint64_t* t, uint32_t tours,
-                     double* L, uint32_t* H, uint32_t* m, orc_seq_stats* st)
+                     orc_xf* L, uint32_t* H, uint32_t* m, orc_seq_stats* st)
 {
     const int dim = P->dim;
     const int64_t n_max = P->n_max;
     const int control_allowed = (P->mode != ORC_MODE_ROSENBLUTH);
+    /* reading R2: own epoch data stands for the whole pool's (N = 1 in Alg 1) */
+    const double pool = (P->mode == ORC_MODE_SHARED) ? (double)P->n_pool : 1.0;
+    const orc_xf one = orc_xf_from_double(1.0);
     orc_walk walk;
     orc_entry* stack = (orc_entry*)malloc(sizeof(orc_entry) * (size_t)(n_max + 1));
     if (!stack || orc_walk_init(&walk, dim, n_max)) { free(stack); return -1; }
@@ -375,8 +431,8 @@ int orc_run_sequence(const orc_params* P, const double* G, uint64_t MG,
         orc_walk_truncate(&walk, 0);
         int64_t depth = 0;
         uint64_t k = 0;
-        double w = 1.0;
-        L[0] += w;          /* W_0 = 1 */
+        orc_xf w = one;
+        L[0] = orc_xf_add(L[0], w);      /* W_0 = 1 */
         H[0] += 1;
         int control = 0;    /* no decision at n = 0 */
         int a;
@@ -391,15 +447,18 @@ int orc_run_sequence(const orc_params* P, const double* G, uint64_t MG,
             int pruned = 0;
             if (control) {
                 int64_t n = walk.n;
-                double est = (G[n] + L[n]) / (double)(MG + (uint64_t)(*m));
-                double r = w / est;
+                /* eqn (6): r = W / [W_n] with [W_n] = sum / tours_seen, evaluated
+                 * as r = (W * tours_seen) / sum (one division) */
+                orc_xf sum = orc_xf_add(G[n], orc_xf_mul(L[n], pool));
+                double tours_seen = (double)(MG + (uint64_t)pool * (uint64_t)(*m));
+                double r = orc_xf_ratio(orc_xf_mul(w, tours_seen), sum);
                 double u = orc_uniform53(B);
                 if (r >= 1.0) {
                     double f = floor(r);
                     double c;
                     if (r != f && u < (f + 1.0) - r) c = f;
                     else c = (r == f) ? f : f + 1.0;
-                    w = w / c;
+                    w = orc_xf_div(w, c);
                     if (c > 1.0) {
                         stack[depth].n = n;
                         stack[depth].remaining = (uint64_t)c - 1;
@@ -410,23 +469,24 @@ int orc_run_sequence(const orc_params* P, const double* G, uint64_t MG,
                         st->copies += (uint64_t)c - 1;
                     }
                 } else {
-                    if (u < r) w = est;
+                    /* survivor: W / r, which is the running average itself */
+                    if (u < r) w = orc_xf_div(sum, tours_seen);
                     else { pruned = 1; st->prunes += 1; }
                 }
             }
 
             int need_backtrack = pruned;
             if (!pruned) {
-                /* Rosenbluth growth (Sec. 1): the j-th free neighbour. */
+                /* Rosenbluth growth (Sec. 1): the j-th free neighbour, W *= a_+ (eqn (2)). */
                 unsigned j = (unsigned)(((uint64_t)B[0] * (uint64_t)a) >> 32);
                 int dir = orc_nth_free(mask, j);
                 st->digest = (st->digest ^ (uint64_t)(dir | (a << 3))) * ORC_FNV_PRIME;
-                w = orc_weight_step(dim, w, a, walk.n);
+                w = orc_xf_mul(w, (double)a);
                 orc_walk_push(&walk, dir);
                 st->steps += 1;
                 steps_this_call += 1;
                 /* arrival: record into the running sums (eqn (4)) */
-                L[walk.n] += w;
+                L[walk.n] = orc_xf_add(L[walk.n], w);
                 H[walk.n] += 1;
                 if (P->step_cap && steps_this_call >= P->step_cap) { capped = 1; break; }
                 if (walk.n == n_max) {
@@ -465,25 +525,27 @@ int orc_run_sequence(const orc_params* P, const double* G, uint64_t MG,
 /*                                                                          */
 /* Shared mode: G[n1], MG[1].  Independent mode: G[N][n1], MG[N].            */
 /* L[N][n1], H[N][n1], m[N], t[N], stats[N].                                 */
+/* ids == NULL runs every sequence 0..N-1; otherwise only ids[0..n_ids-1].   */
 /* ------------------------------------------------------------------------ */
-/* ids == NULL runs every sequence 0..N-1; otherwise only ids[0..n_ids-1]. */
-int orc_run_epoch(const orc_params* P, int64_t N, const double* G, const uint64_t* MG,
-                  uint64_t* t, uint32_t tours, double* L, uint32_t* H, uint32_t* m,
+int orc_run_epoch(const orc_params* P, int64_t N, const orc_xf* G, const uint64_t* MG,
+                  uint64_t* t, uint32_t tours, orc_xf* L, uint32_t* H, uint32_t* m,
                   orc_seq_stats* stats, const int64_t* ids, int64_t n_ids, int threads)
 {
     const int64_t n1 = P->n_max + 1;
     const int64_t count = ids ? n_ids : N;
     int any_capped = 0;
+    orc_params Q = *P;
+    Q.n_pool = (uint64_t)N;
 #ifdef _OPENMP
     if (threads <= 0) threads = omp_get_max_threads();
 #pragma omp parallel for schedule(dynamic, 1) num_threads(threads) reduction(|:any_capped)
 #endif
     for (int64_t i = 0; i < count; ++i) {
         const int64_t s = ids ? ids[i] : i;
-        const double* Gs = G;
+        const orc_xf* Gs = G;
         uint64_t Ms = MG ? MG[0] : 0;
         if (P->mode == ORC_MODE_INDEPENDENT) { Gs = G + s * n1; Ms = MG[s]; }
-        int rc = orc_run_sequence(P, Gs, Ms, (uint32_t)s, &t[s], tours,
+        int rc = orc_run_sequence(&Q, Gs, Ms, (uint32_t)s, &t[s], tours,
                                   L + s * n1, H + s * n1, &m[s], &stats[s]);
         if (rc != 0) any_capped |= 1;
     }
@@ -494,27 +556,31 @@ int orc_run_epoch(const orc_params* P, int64_t N, const double* G, const uint64_
 /* ------------------------------------------------------------------------ */
 /* Merge (reading R9): the aligned pairwise tree over sequences.             */
 /* ------------------------------------------------------------------------ */
-static double orc_pairwise(const double* L, int64_t n1, int64_t n, int64_t N,
+static orc_xf orc_pairwise(const orc_xf* L, int64_t n1, int64_t n, int64_t N,
                            int64_t lo, int64_t len)
 {
-    if (len == 1) return (lo < N) ? L[lo * n1 + n] : 0.0;
+    if (len == 1) {
+        if (lo < N) return L[lo * n1 + n];
+        orc_xf z = { 0.0, 0, 0 };
+        return z;
+    }
     int64_t half = len / 2;
-    double left = orc_pairwise(L, n1, n, N, lo, half);
-    double right = orc_pairwise(L, n1, n, N, lo + half, half);
-    return left + right;
+    orc_xf left = orc_pairwise(L, n1, n, N, lo, half);
+    orc_xf right = orc_pairwise(L, n1, n, N, lo + half, half);
+    return orc_xf_add(left, right);
 }
 
 /* Shared mode: G[n] += tree(L[.][n]); HG[n] += sum H[.][n]; MG += sum m.
  * Independent mode: per sequence, G[s][n] += L[s][n] (and the same for HG, MG).
  * Afterwards L, H and m are zero. */
-void orc_merge(const orc_params* P, int64_t N, double* L, uint32_t* H, uint32_t* m,
-               double* G, uint64_t* HG, uint64_t* MG)
+void orc_merge(const orc_params* P, int64_t N, orc_xf* L, uint32_t* H, uint32_t* m,
+               orc_xf* G, uint64_t* HG, uint64_t* MG)
 {
     const int64_t n1 = P->n_max + 1;
     if (P->mode == ORC_MODE_INDEPENDENT) {
         for (int64_t s = 0; s < N; ++s) {
             for (int64_t n = 0; n < n1; ++n) {
-                G[s * n1 + n] += L[s * n1 + n];
+                G[s * n1 + n] = orc_xf_add(G[s * n1 + n], L[s * n1 + n]);
                 HG[s * n1 + n] += H[s * n1 + n];
             }
             MG[s] += m[s];
@@ -523,7 +589,7 @@ void orc_merge(const orc_params* P, int64_t N, double* L, uint32_t* H, uint32_t*
         int64_t P2 = 1;
         while (P2 < N) P2 <<= 1;
         for (int64_t n = 0; n < n1; ++n) {
-            G[n] += orc_pairwise(L, n1, n, N, 0, P2);
+            G[n] = orc_xf_add(G[n], orc_pairwise(L, n1, n, N, 0, P2));
             uint64_t h = 0;
             for (int64_t s = 0; s < N; ++s) h += H[s * n1 + n];
             HG[n] += h;
@@ -532,17 +598,16 @@ void orc_merge(const orc_params* P, int64_t N, double* L, uint32_t* H, uint32_t*
         for (int64_t s = 0; s < N; ++s) mm += m[s];
         MG[0] += mm;
     }
-    memset(L, 0, sizeof(double) * (size_t)(N * n1));
+    memset(L, 0, sizeof(orc_xf) * (size_t)(N * n1));
     memset(H, 0, sizeof(uint32_t) * (size_t)(N * n1));
     memset(m, 0, sizeof(uint32_t) * (size_t)N);
 }
 
-/* Estimates (eqn (4) in scaled units): log c_n = ln G_n - ln M + E_n ln 2. */
-void orc_log_estimates(int dim, int64_t n_max, const double* G, uint64_t MG, double* out)
+/* Estimates (eqn (4)): log c_n = ln G_n.m + G_n.e ln 2 - ln M. */
+void orc_log_estimates(int64_t n_max, const orc_xf* G, uint64_t MG, double* out)
 {
     for (int64_t n = 0; n <= n_max; ++n) {
-        out[n] = log(G[n]) - log((double)MG)
-               + (double)orc_scale_exponent(dim, n) * 0.69314718055994530942;
+        out[n] = log(G[n].m) + (double)G[n].e * 0.69314718055994530942 - log((double)MG);
     }
 }
 
@@ -550,20 +615,20 @@ void orc_log_estimates(int dim, int64_t n_max, const double* G, uint64_t MG, dou
 /* Plain flatPERM written recursively in the order Sec. 2 describes it: the  */
 /* arrival records, the decision makes c copies, each copy grows on.  Used  */
 /* only as a cross-check of the iterative form above (one sequence, one      */
-/* epoch).  The state of the recursion lives in `orc_rec`.                   */
+/* epoch).  The state of the recursion lives in `orc_recur`.                 */
 /* ------------------------------------------------------------------------ */
 typedef struct {
     const orc_params* P;
     orc_walk walk;
-    double* L; uint32_t* H;
+    orc_xf* L; uint32_t* H;
     uint64_t m;        /* tours so far, including the current one */
     uint64_t t;        /* current tour index */
     uint64_t k;        /* events drawn in the current tour */
-} orc_rec;
+} orc_recur;
 
-static void orc_rec_arrive(orc_rec* R, double w);
+static void orc_rec_arrive(orc_recur* R, orc_xf w);
 
-static void orc_rec_grow(orc_rec* R, double w, int control)
+static void orc_rec_grow(orc_recur* R, orc_xf w, int control)
 {
     const orc_params* P = R->P;
     uint32_t B[4];
@@ -572,16 +637,15 @@ static void orc_rec_grow(orc_rec* R, double w, int control)
     uint64_t c = 1;
     if (control) {
         int64_t n = R->walk.n;
-        double est = R->L[n] / (double)R->m;
-        double r = w / est;
+        double r = orc_xf_ratio(orc_xf_mul(w, (double)R->m), R->L[n]);
         double u = orc_uniform53(B);
         if (r >= 1.0) {
             double f = floor(r);
             double cf = (r != f && u < (f + 1.0) - r) ? f : ceil(r);
             c = (uint64_t)cf;
-            w = w / cf;
+            w = orc_xf_div(w, cf);
         } else if (u < r) {
-            w = est;
+            w = orc_xf_div(R->L[n], (double)R->m);
         } else {
             return;    /* pruned */
         }
@@ -593,16 +657,16 @@ static void orc_rec_grow(orc_rec* R, double w, int control)
     int dir = orc_nth_free(mask, j);
     int64_t n = R->walk.n;
     orc_walk_push(&R->walk, dir);
-    orc_rec_arrive(R, orc_weight_step(P->dim, w, a, n));
+    orc_rec_arrive(R, orc_xf_mul(w, (double)a));
     orc_walk_truncate(&R->walk, n);
     /* copies 2..c grow independently, each from a fresh event */
     for (uint64_t i = 1; i < c; ++i) orc_rec_grow(R, w, 0);
 }
 
-static void orc_rec_arrive(orc_rec* R, double w)
+static void orc_rec_arrive(orc_recur* R, orc_xf w)
 {
     int64_t n = R->walk.n;
-    R->L[n] += w;
+    R->L[n] = orc_xf_add(R->L[n], w);
     R->H[n] += 1;
     if (n == R->P->n_max) return;
     int a;
@@ -611,18 +675,19 @@ static void orc_rec_arrive(orc_rec* R, double w)
     orc_rec_grow(R, w, R->P->mode != ORC_MODE_ROSENBLUTH);
 }
 
-int orc_plain_recursive(const orc_params* P, uint32_t tours, double* L, uint32_t* H)
+int orc_plain_recursive(const orc_params* P, uint32_t tours, orc_xf* L, uint32_t* H)
 {
-    orc_rec R;
+    orc_recur R;
     R.P = P; R.L = L; R.H = H; R.m = 0; R.t = 0; R.k = 0;
     if (orc_walk_init(&R.walk, P->dim, P->n_max)) return -1;
+    const orc_xf one = orc_xf_from_double(1.0);
     for (uint32_t i = 0; i < tours; ++i) {
         R.m += 1;
         R.t = i;
         R.k = 0;
-        L[0] += 1.0;
+        L[0] = orc_xf_add(L[0], one);
         H[0] += 1;
-        orc_rec_grow(&R, 1.0, 0);
+        orc_rec_grow(&R, one, 0);
     }
     orc_walk_free(&R.walk);
     return 0;
@@ -633,22 +698,22 @@ int orc_plain_recursive(const orc_params* P, uint32_t tours, double* L, uint32_t
 /* length <= n_max is grown once, through the same free-neighbour scan and   */
 /* the same weight update the sampler uses.                                  */
 /*   count[n]   : number of chains of length n reached (must be c_n)         */
-/*   bad[0]     : chains whose scaled weight * 2^E_n differs from prod a_+   */
+/*   bad[0]     : chains whose weight differs from prod a_+                  */
 /* The product prod a_+ is carried here as an exact integer, independently   */
 /* of the floating-point update, so this checks eqns (1)-(3) chain by chain. */
 /* ------------------------------------------------------------------------ */
-static void orc_force_rec(orc_walk* W, int64_t n_max, double w, uint64_t prod,
+static void orc_force_rec(orc_walk* W, int64_t n_max, orc_xf w, uint64_t prod,
                           uint64_t* count, uint64_t* bad)
 {
     int64_t n = W->n;
     count[n] += 1;
-    if (ldexp(w, (int)orc_scale_exponent(W->dim, n)) != (double)prod) bad[0] += 1;
+    if (ldexp(w.m, w.e) != (double)prod) bad[0] += 1;
     if (n == n_max) return;
     int a;
     unsigned mask = orc_free_mask(W, &a);
     for (int j = 0; j < a; ++j) {
         int dir = orc_nth_free(mask, (unsigned)j);
-        double w2 = orc_weight_step(W->dim, w, a, n);
+        orc_xf w2 = orc_xf_mul(w, (double)a);
         orc_walk_push(W, dir);
         orc_force_rec(W, n_max, w2, prod * (uint64_t)a, count, bad);
         orc_walk_truncate(W, n);
@@ -661,7 +726,7 @@ int orc_forced_enumerate(int dim, int64_t n_max, uint64_t* count, uint64_t* bad)
     if (orc_walk_init(&W, dim, n_max)) return -1;
     memset(count, 0, sizeof(uint64_t) * (size_t)(n_max + 1));
     bad[0] = 0;
-    orc_force_rec(&W, n_max, 1.0, 1, count, bad);
+    orc_force_rec(&W, n_max, orc_xf_from_double(1.0), 1, count, bad);
     orc_walk_free(&W);
     return 0;
 }

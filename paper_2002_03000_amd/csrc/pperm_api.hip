@@ -1,0 +1,445 @@
+// Host side of libpperm.so: the C ABI declared in include/pperm.h.
+//
+// The library owns no device memory: the caller hands in one workspace (a
+// torch tensor in the Python binding) and the library lays its state out in
+// it.  Every device operation is enqueued on the caller's stream.
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "pperm.h"
+#include "pperm_internal.h"
+
+using namespace pperm;
+
+struct pperm_ctx {
+    pperm_config cfg;
+    hipStream_t stream;
+    unsigned char* ws;
+    size_t ws_bytes;
+    pperm_layout lay;
+    int device;
+    uint32_t team_lanes;      // TS: lanes per walk
+    uint32_t slots_log2;
+    uint32_t lds_team_bytes;
+    uint32_t workgroups;
+    uint64_t merged_tours;    // pooled tours merged so far (per sequence in independent mode)
+    uint64_t open_tours;      // tours per sequence run since the last merge
+    int sticky_error;
+};
+
+namespace {
+
+thread_local char g_last_error[256] = "";
+
+int device_error(hipError_t e, const char* what) {
+    snprintf(g_last_error, sizeof(g_last_error), "%s: %s", what, hipGetErrorString(e));
+    return PPERM_EDEVICE;
+}
+
+#define HIP_TRY(expr)                                   \
+    do {                                                \
+        hipError_t e_ = (expr);                         \
+        if (e_ != hipSuccess) return device_error(e_, #expr); \
+    } while (0)
+
+constexpr uint32_t kMaxNmax = 32766;
+constexpr uint32_t kMaxSlots = 65536;
+constexpr uint32_t kMaxStackSlots = 65536;
+constexpr uint32_t kLdsLimit = 65536;    // bytes of LDS one workgroup may take
+constexpr uint32_t kDefaultCap = 1u << 31;
+
+uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+bool is_pow2(uint32_t x) { return x && !(x & (x - 1)); }
+
+uint32_t log2u(uint32_t x) {
+    uint32_t r = 0;
+    while ((1u << r) < x) ++r;
+    return r;
+}
+
+uint32_t key_bytes(uint32_t dim) { return dim == 2 ? 4u : 8u; }
+
+// Resolved tuning choices for a configuration (the "auto" values included).
+struct Shape {
+    uint32_t team_lanes;
+    uint32_t slots;
+    uint32_t lds_team_bytes;
+    uint32_t walks_per_wave;
+};
+
+int resolve_shape(const pperm_config* c, Shape* sh) {
+    uint32_t slots = c->hash_slots;
+    if (slots == 0) {
+        slots = 64;
+        while (slots < 2u * (c->n_max + 1u)) slots <<= 1;
+    }
+    if (!is_pow2(slots) || slots > kMaxSlots || slots < 2u * (c->n_max + 1u)) return PPERM_EINVAL;
+    sh->slots = slots;
+    sh->lds_team_bytes = (uint32_t)align_up((uint64_t)slots * key_bytes(c->dim) +
+                                            2ull * (c->n_max + 1u), 16);
+    uint32_t wpw = c->walks_per_wave;
+    if (wpw == 0) {
+        // default shape, narrowed until the walks of one workgroup fit in LDS
+        wpw = (c->dim == 2) ? 4u : 2u;
+        while (wpw > 1 && (uint64_t)sh->lds_team_bytes * wpw > kLdsLimit) wpw >>= 1;
+    }
+    if (!is_pow2(wpw) || wpw > (c->dim == 2 ? 16u : 8u)) return PPERM_EINVAL;
+    sh->walks_per_wave = wpw;
+    sh->team_lanes = 64u / wpw;
+    if ((uint64_t)sh->lds_team_bytes * wpw > kLdsLimit) return PPERM_EINVAL;
+    return PPERM_OK;
+}
+
+int validate(const pperm_config* c) {
+    if (!c) return PPERM_EINVAL;
+    if (c->struct_size != sizeof(pperm_config)) return PPERM_EINVAL;
+    if (c->dim != 2 && c->dim != 3) return PPERM_EINVAL;
+    if (c->n_max < 1 || c->n_max > kMaxNmax) return PPERM_EINVAL;
+    if (c->n_sequences < 1) return PPERM_EINVAL;
+    if (c->mode > PPERM_ROSENBLUTH) return PPERM_EINVAL;
+    if (c->flags != 0) return PPERM_EINVAL;
+    Shape sh;
+    return resolve_shape(c, &sh);
+}
+
+// Lay the state out in the workspace; every array 256-byte aligned.
+void compute_layout(const pperm_config* c, pperm_layout* L) {
+    const uint64_t N = c->n_sequences;
+    const uint64_t row = align_up(c->n_max + 1u, 16);
+    const bool indep = (c->mode == PPERM_INDEPENDENT);
+    Shape sh;
+    resolve_shape(c, &sh);
+    const uint64_t stack_slots =
+        align_up(N < kMaxStackSlots ? N : kMaxStackSlots, sh.walks_per_wave);
+    const uint64_t chunks = (N + 63) / 64;
+    uint64_t off = 0;
+    auto take = [&](uint64_t bytes) {
+        uint64_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    };
+    memset(L, 0, sizeof(*L));
+    L->row = (uint32_t)row;
+    L->stack_slots = (uint32_t)stack_slots;
+    // state that create() zeroes comes first and is contiguous
+    L->G = take((indep ? N : 1) * row * sizeof(SumRec));
+    L->HG = take((indep ? N : 1) * row * 8);
+    L->MG = take((indep ? N : 1) * 8);
+    L->L = take(N * row * sizeof(SumRec));
+    L->m = take(N * 4);
+    L->t = take(N * 8);
+    L->stats = take(N * STATS_WORDS * 8);
+    L->ctrl = take(CTRL_WORDS * 4);
+    // private scratch, not zeroed: copy stacks, merge partials (records + counts, x2)
+    L->stack = take(stack_slots * c->n_max * sizeof(StackEntry));
+    L->scratch = take(2 * chunks * row * (sizeof(SumRec) + 8));
+    L->total = off;
+}
+
+template <typename T>
+T* at(pperm_ctx* x, uint64_t off) {
+    return reinterpret_cast<T*>(x->ws + off);
+}
+
+int check_device_errors(pperm_ctx* x) {
+    uint32_t err = 0;
+    HIP_TRY(hipMemcpyAsync(&err, at<uint32_t>(x, x->lay.ctrl) + CTRL_ERR, sizeof(err),
+                           hipMemcpyDeviceToHost, x->stream));
+    HIP_TRY(hipStreamSynchronize(x->stream));
+    if (err & ERR_RANGE) x->sticky_error = PPERM_ERANGE;
+    else if (err & ERR_CAP) x->sticky_error = PPERM_EOVERFLOW;
+    return x->sticky_error;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pperm_strerror(int code) {
+    switch (code) {
+        case PPERM_OK: return "success";
+        case PPERM_EINVAL: return "invalid argument or configuration";
+        case PPERM_ENOMEM: return "out of host memory";
+        case PPERM_EDEVICE: return "HIP device error";
+        case PPERM_ESTATE: return "call out of order";
+        case PPERM_ERANGE: return "scaled weight out of range";
+        case PPERM_EOVERFLOW: return "step cap or counter overflow";
+        default: return "unknown error";
+    }
+}
+
+const char* pperm_last_device_error(void) { return g_last_error; }
+
+int pperm_workspace_bytes(const pperm_config* cfg, size_t* bytes) {
+    if (!bytes) return PPERM_EINVAL;
+    int rc = validate(cfg);
+    if (rc) return rc;
+    pperm_layout L;
+    compute_layout(cfg, &L);
+    *bytes = (size_t)L.total;
+    return PPERM_OK;
+}
+
+int pperm_create(const pperm_config* cfg, void* d_workspace, size_t bytes, void* hip_stream,
+                 pperm_ctx** out) {
+    if (!out || !d_workspace) return PPERM_EINVAL;
+    *out = nullptr;
+    int rc = validate(cfg);
+    if (rc) return rc;
+    if (((uintptr_t)d_workspace & 255u) != 0) return PPERM_EINVAL;
+    pperm_layout L;
+    compute_layout(cfg, &L);
+    if (bytes < L.total) return PPERM_EINVAL;
+    Shape sh;
+    resolve_shape(cfg, &sh);
+
+    pperm_ctx* x = new (std::nothrow) pperm_ctx();
+    if (!x) return PPERM_ENOMEM;
+    x->cfg = *cfg;
+    x->stream = (hipStream_t)hip_stream;
+    x->ws = (unsigned char*)d_workspace;
+    x->ws_bytes = bytes;
+    x->lay = L;
+    x->team_lanes = sh.team_lanes;
+    x->slots_log2 = log2u(sh.slots);
+    x->lds_team_bytes = sh.lds_team_bytes;
+
+    hipError_t e = hipGetDevice(&x->device);
+    if (e != hipSuccess) { delete x; return device_error(e, "hipGetDevice"); }
+    int cus = 0;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, x->device);
+    if (e != hipSuccess) { delete x; return device_error(e, "hipDeviceGetAttribute"); }
+    const uint32_t lds_wg = sh.lds_team_bytes * sh.walks_per_wave;
+    int per_cu = 0;
+    e = run_kernel_lds_ok(cfg->dim, sh.team_lanes, lds_wg, &per_cu);
+    if (e != hipSuccess) { delete x; return device_error(e, "occupancy"); }
+    if (per_cu < 1) { delete x; return PPERM_EINVAL; }
+    uint64_t wgs = ((uint64_t)cfg->n_sequences + sh.walks_per_wave - 1) / sh.walks_per_wave;
+    const uint64_t resident = (uint64_t)per_cu * (uint64_t)cus;
+    if (wgs > resident) wgs = resident;
+    const uint64_t by_stack = L.stack_slots / sh.walks_per_wave;
+    if (wgs > by_stack) wgs = by_stack;
+    x->workgroups = (uint32_t)wgs;
+
+    // zero the state (G .. ctrl are contiguous) and seed the digests
+    const uint64_t zero_bytes = L.ctrl + CTRL_WORDS * 4 - L.G;
+    e = launch_init_state(at<uint64_t>(x, L.stats), cfg->n_sequences, x->ws + L.G, zero_bytes,
+                          x->stream);
+    if (e != hipSuccess) { delete x; return device_error(e, "init_state"); }
+    *out = x;
+    return PPERM_OK;
+}
+
+int pperm_run_tours(pperm_ctx* x, uint32_t tours) {
+    if (!x || tours == 0) return PPERM_EINVAL;
+    const uint64_t N = x->cfg.n_sequences;
+    const uint64_t per_seq_total = x->open_tours + tours;
+    // r <= M + m bounds every copy count; keep M + m and every tour index in 32 bits
+    const uint64_t pooled = (x->cfg.mode == PPERM_SHARED) ? x->merged_tours + N * per_seq_total
+                                                          : x->merged_tours + per_seq_total;
+    if (pooled > 0xFFFFFFFFull || per_seq_total > 0xFFFFFFFFull) return PPERM_EOVERFLOW;
+
+    RunArgs a;
+    a.G = at<SumRec>(x, x->lay.G);
+    a.MG = at<uint64_t>(x, x->lay.MG);
+    a.L = at<SumRec>(x, x->lay.L);
+    a.m = at<uint32_t>(x, x->lay.m);
+    a.t = at<uint64_t>(x, x->lay.t);
+    a.stats = at<uint64_t>(x, x->lay.stats);
+    a.stack = at<StackEntry>(x, x->lay.stack);
+    a.ctrl = at<uint32_t>(x, x->lay.ctrl);
+    a.N = x->cfg.n_sequences;
+    a.n_max = x->cfg.n_max;
+    a.row = x->lay.row;
+    a.tours = tours;
+    a.mode = x->cfg.mode;
+    a.slots_log2 = x->slots_log2;
+    a.lds_team_bytes = x->lds_team_bytes;
+    a.key0 = (uint32_t)x->cfg.seed;
+    a.key1 = (uint32_t)(x->cfg.seed >> 32) ^ x->cfg.stream_id;
+    // watchdog: a sequence may take at most step_cap growth steps per call; by
+    // default 4096 times the flat-histogram expectation of one sample per length
+    // per tour, so that a runaway enrichment tree ends with PPERM_EOVERFLOW
+    uint64_t cap = x->cfg.step_cap;
+    if (cap == 0) {
+        cap = 4096ull * tours * (x->cfg.n_max + 1ull);
+        if (cap > kDefaultCap) cap = kDefaultCap;
+    }
+    a.step_cap = (uint32_t)cap;
+
+    HIP_TRY(launch_reset_ctrl(a.ctrl, x->stream));
+    const uint32_t wpw = 64u / x->team_lanes;
+    HIP_TRY(launch_run(a, x->cfg.dim, x->team_lanes, x->workgroups, x->lds_team_bytes * wpw,
+                       x->stream));
+    x->open_tours = per_seq_total;
+    return PPERM_OK;
+}
+
+int pperm_merge_epoch(pperm_ctx* x) {
+    if (!x) return PPERM_EINVAL;
+    const uint32_t N = x->cfg.n_sequences;
+    const uint32_t row = x->lay.row;
+    SumRec* L = at<SumRec>(x, x->lay.L);
+    uint32_t* m = at<uint32_t>(x, x->lay.m);
+    SumRec* G = at<SumRec>(x, x->lay.G);
+    uint64_t* HG = at<uint64_t>(x, x->lay.HG);
+    uint64_t* MG = at<uint64_t>(x, x->lay.MG);
+    if (x->cfg.mode == PPERM_INDEPENDENT) {
+        HIP_TRY(launch_merge_independent(L, m, G, HG, MG, N, row, x->stream));
+        x->merged_tours += x->open_tours;
+        x->open_tours = 0;
+        return PPERM_OK;
+    }
+    HIP_TRY(launch_merge_counts(m, N, MG, m, x->stream));
+    // aligned pairwise tree over sequences, 64 rows per pass
+    const uint64_t chunks = (N + 63) / 64;
+    SumRec* bufd[2] = {at<SumRec>(x, x->lay.scratch), at<SumRec>(x, x->lay.scratch) + chunks * row};
+    uint64_t* bufh[2] = {reinterpret_cast<uint64_t*>(bufd[1] + chunks * row),
+                         reinterpret_cast<uint64_t*>(bufd[1] + chunks * row) + chunks * row};
+    MergeArgs a;
+    a.in = L;
+    a.hin = nullptr;
+    a.zero = L;
+    a.rows = N;
+    a.row = row;
+    a.ncols = x->cfg.n_max + 1;
+    int cur = 0;
+    for (;;) {
+        const bool final_pass = (a.rows <= 64);
+        a.out = final_pass ? G : bufd[cur];
+        a.hout = final_pass ? HG : bufh[cur];
+        a.accumulate = final_pass ? 1u : 0u;
+        HIP_TRY(launch_merge_pass(a, x->stream));
+        if (final_pass) break;
+        a.in = bufd[cur];
+        a.hin = bufh[cur];
+        a.zero = nullptr;
+        a.rows = (uint32_t)((a.rows + 63) / 64);
+        cur ^= 1;
+    }
+    x->merged_tours += (uint64_t)N * x->open_tours;
+    x->open_tours = 0;
+    return PPERM_OK;
+}
+
+int pperm_estimates(pperm_ctx* x, double* log_cn, uint64_t* hist, uint64_t* tours, size_t len) {
+    if (!x || !log_cn) return PPERM_EINVAL;
+    const uint32_t n1 = x->cfg.n_max + 1;
+    if (len < n1) return PPERM_EINVAL;
+    int rc = check_device_errors(x);
+    if (rc) return rc;
+    const uint32_t row = x->lay.row;
+    const double ln2 = 0.69314718055994530942;
+    if (x->cfg.mode == PPERM_INDEPENDENT) {
+        const uint32_t N = x->cfg.n_sequences;
+        std::vector<SumRec> G((size_t)N * row);
+        std::vector<uint64_t> HG((size_t)N * row), MG(N);
+        HIP_TRY(hipMemcpy(G.data(), at<SumRec>(x, x->lay.G), G.size() * sizeof(SumRec),
+                          hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(HG.data(), at<uint64_t>(x, x->lay.HG), HG.size() * 8,
+                          hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(MG.data(), at<uint64_t>(x, x->lay.MG), MG.size() * 8,
+                          hipMemcpyDeviceToHost));
+        uint64_t total = 0;
+        for (uint32_t s = 0; s < N; ++s) {
+            if (MG[s] == 0) return PPERM_ESTATE;
+            total += MG[s];
+        }
+        std::vector<double> lg(N);
+        for (uint32_t n = 0; n < n1; ++n) {
+            // eqn (7): the mean over sequences of each sequence's own average,
+            // summed in the log domain (the averages span any range)
+            double top = -INFINITY;
+            uint64_t h = 0;
+            for (uint32_t s = 0; s < N; ++s) {
+                const SumRec& g = G[(size_t)s * row + n];
+                lg[s] = log(g.m) + g.e * ln2 - log((double)MG[s]);
+                if (lg[s] > top) top = lg[s];
+                h += HG[(size_t)s * row + n];
+            }
+            double acc = 0.0;
+            if (top > -INFINITY)
+                for (uint32_t s = 0; s < N; ++s) acc += exp(lg[s] - top);
+            log_cn[n] = (top > -INFINITY) ? top + log(acc) - log((double)N) : -INFINITY;
+            if (hist) hist[n] = h;
+        }
+        if (tours) *tours = total;
+        return PPERM_OK;
+    }
+    std::vector<SumRec> G(n1);
+    std::vector<uint64_t> HG(n1);
+    uint64_t MG = 0;
+    HIP_TRY(hipMemcpy(G.data(), at<SumRec>(x, x->lay.G), n1 * sizeof(SumRec), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(HG.data(), at<uint64_t>(x, x->lay.HG), n1 * 8, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(&MG, at<uint64_t>(x, x->lay.MG), 8, hipMemcpyDeviceToHost));
+    if (MG == 0) return PPERM_ESTATE;
+    for (uint32_t n = 0; n < n1; ++n) {
+        log_cn[n] = log(G[n].m) + G[n].e * ln2 - log((double)MG);
+        if (hist) hist[n] = HG[n];
+    }
+    if (tours) *tours = MG;
+    return PPERM_OK;
+}
+
+int pperm_sequence_stats(pperm_ctx* x, pperm_seq_stats* out, size_t count) {
+    if (!x || !out || count < x->cfg.n_sequences) return PPERM_EINVAL;
+    HIP_TRY(hipStreamSynchronize(x->stream));
+    HIP_TRY(hipMemcpy(out, at<uint64_t>(x, x->lay.stats),
+                      (size_t)x->cfg.n_sequences * sizeof(pperm_seq_stats), hipMemcpyDeviceToHost));
+    return PPERM_OK;
+}
+
+int pperm_stats(pperm_ctx* x, pperm_seq_stats* total) {
+    if (!x || !total) return PPERM_EINVAL;
+    std::vector<pperm_seq_stats> all(x->cfg.n_sequences);
+    int rc = pperm_sequence_stats(x, all.data(), all.size());
+    if (rc) return rc;
+    memset(total, 0, sizeof(*total));
+    for (const auto& s : all) {
+        total->steps += s.steps;
+        total->events += s.events;
+        total->enrich += s.enrich;
+        total->copies += s.copies;
+        total->prunes += s.prunes;
+        total->traps += s.traps;
+        total->tours += s.tours;
+        if (s.max_depth > total->max_depth) total->max_depth = s.max_depth;
+        total->digest ^= s.digest;
+        total->capped += s.capped;
+    }
+    return PPERM_OK;
+}
+
+int pperm_sync(pperm_ctx* x) {
+    if (!x) return PPERM_EINVAL;
+    return check_device_errors(x);
+}
+
+int pperm_layout_of(const pperm_ctx* x, pperm_layout* out) {
+    if (!x || !out) return PPERM_EINVAL;
+    *out = x->lay;
+    return PPERM_OK;
+}
+
+int pperm_launch_shape(const pperm_ctx* x, uint32_t* walks_per_wave, uint32_t* hash_slots,
+                       uint32_t* workgroups) {
+    if (!x) return PPERM_EINVAL;
+    if (walks_per_wave) *walks_per_wave = 64u / x->team_lanes;
+    if (hash_slots) *hash_slots = 1u << x->slots_log2;
+    if (workgroups) *workgroups = x->workgroups;
+    return PPERM_OK;
+}
+
+int pperm_destroy(pperm_ctx* x) {
+    if (!x) return PPERM_EINVAL;
+    delete x;
+    return PPERM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,89 @@
+// Internal interface between the host C-ABI layer and the gfx950 kernels of
+// libpperm.so.  Not installed, not part of the ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pperm {
+
+// Error bits a kernel may raise in ctrl[1].
+enum : uint32_t { ERR_CAP = 1u, ERR_RANGE = 2u };
+
+// Exponents beyond this magnitude are reported as PPERM_ERANGE.
+constexpr int32_t EXP_LIMIT = 1 << 30;
+
+// Control words in the workspace.
+enum : uint32_t { CTRL_QUEUE = 0, CTRL_ERR = 1, CTRL_WORDS = 16 };
+
+// Modes (same values as the ABI).
+enum : uint32_t { MODE_SHARED = 0, MODE_INDEPENDENT = 1, MODE_ROSENBLUTH = 2 };
+
+constexpr int STATS_WORDS = 10;
+enum : int { ST_STEPS = 0, ST_EVENTS, ST_ENRICH, ST_COPIES, ST_PRUNES, ST_TRAPS,
+             ST_TOURS, ST_MAXDEPTH, ST_DIGEST, ST_CAPPED };
+
+// 16-byte record of an extended-range sum: value = m * 2^e (m in [0.5, 1) or
+// m = 0 and e = 0) and, for the per-sequence sums, the sample count h.
+struct __attribute__((aligned(16))) SumRec {
+    double m;
+    int32_t e;
+    uint32_t h;
+};
+
+// 32-byte pending-copy entry.
+struct __attribute__((aligned(16))) StackEntry {
+    uint32_t n;
+    uint32_t remaining;
+    int32_t e;
+    uint32_t pad0;
+    double m;
+    uint64_t pad1;
+};
+
+struct RunArgs {
+    const SumRec* G;      // shared: [row]; independent: [N][row]
+    const uint64_t* MG;   // shared: [1];   independent: [N]
+    SumRec* L;            // [N][row]
+    uint32_t* m;          // [N]
+    uint64_t* t;          // [N]
+    uint64_t* stats;      // [N][STATS_WORDS]
+    StackEntry* stack;    // [stack_slots][n_max]
+    uint32_t* ctrl;       // CTRL_WORDS
+    uint32_t N;
+    uint32_t n_max;
+    uint32_t row;
+    uint32_t tours;
+    uint32_t mode;
+    uint32_t slots_log2;
+    uint32_t lds_team_bytes;
+    uint32_t key0, key1;
+    uint32_t step_cap;
+};
+
+struct MergeArgs {
+    const SumRec* in;      // [rows][row]
+    SumRec* out;           // [ceil(rows/64)][row], or G when final
+    uint64_t* hout;        // [ceil(rows/64)][row], or HG when final
+    const uint64_t* hin;   // later passes: [rows][row]; first pass: nullptr (counts in `in`)
+    SumRec* zero;          // input to clear after reading (first pass) or nullptr
+    uint32_t rows;
+    uint32_t row;
+    uint32_t ncols;        // n_max + 1
+    uint32_t accumulate;   // final pass: out[n] = out[n] + tree
+};
+
+// Launchers (pperm_kernels.hip).  All return the hipError_t of the launch.
+hipError_t launch_reset_ctrl(uint32_t* ctrl, hipStream_t s);
+hipError_t launch_init_state(uint64_t* stats, uint32_t N, void* zero_base, size_t zero_bytes,
+                             hipStream_t s);
+hipError_t launch_run(const RunArgs& a, uint32_t dim, uint32_t team_lanes, uint32_t workgroups,
+                      uint32_t lds_bytes, hipStream_t s);
+hipError_t run_kernel_lds_ok(uint32_t dim, uint32_t team_lanes, uint32_t lds_bytes,
+                             int* blocks_per_cu);
+hipError_t launch_merge_pass(const MergeArgs& a, hipStream_t s);
+hipError_t launch_merge_counts(const uint32_t* m, uint32_t N, uint64_t* MG, uint32_t* zero_m,
+                               hipStream_t s);
+hipError_t launch_merge_independent(SumRec* L, uint32_t* m, SumRec* G, uint64_t* HG, uint64_t* MG,
+                                    uint32_t N, uint32_t row, hipStream_t s);
+
+}  // namespace pperm

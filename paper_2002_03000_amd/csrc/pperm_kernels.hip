@@ -1,0 +1,719 @@
+// gfx950 kernels of parallel flatPERM (Campbell & Janse van Rensburg,
+// "Parallel PERM"): Rosenbluth growth with a_+ occupancy scans (Sec. 1,
+// eqns (1)-(2)), flatPERM prune/enrich against the running averages (Sec. 2,
+// eqn (6)), accumulation of the sample sums (eqn (4)), and the merge of the
+// per-sequence sums into the pooled sums of Algorithm 2 (Sec. 3, Fig. 1).
+//
+// Execution model.  A "team" of TS lanes of one 64-lane wavefront owns one
+// walk, i.e. one flatPERM sequence at a time; 64/TS walks share a wave.  Every
+// lane of a team holds the team's walk state (so every lane can take every
+// decision and no broadcast is needed), and the lanes split the parallel parts
+// of a step between them:
+//   - the occupancy scan: lane (dir, off) reads slot home(dir)+off+W*round of
+//     the walk's open-addressing table, so the 2d neighbours and W consecutive
+//     probe positions per neighbour are looked up in one LDS instruction and
+//     resolved with wave ballots;
+//   - the random numbers: lane i of a team computes the Philox4x32-10 block
+//     of event k0+i, so one pass of the (quarter-rate) multiplies serves TS
+//     events; a step fetches its block with one lane shuffle per word;
+//   - the LIFO deletion of abandoned sites after a backtrack.
+// The walk's occupancy table (packed int16 coordinates, linear probing,
+// restored exactly by LIFO deletion through remembered slot ids) and the
+// slot-id array live in LDS.  The pending-copy stack lives in global memory
+// with its top entry in registers.  Sequence sums L, H live in global memory
+// (L2-resident); the values for the next length are prefetched one step ahead.
+//
+// Determinism.  Every floating-point decision uses the same IEEE operations
+// in the same order as the reading of the method these kernels implement
+// (no contraction: the library is built with -ffp-contract=off), and the
+// random numbers are a pure function of (seed, sequence, tour, event).  The
+// launch shape therefore never changes a result.
+#include "pperm_internal.h"
+
+namespace pperm {
+namespace {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): 10 rounds, Weyl key schedule.
+// ---------------------------------------------------------------------------
+constexpr uint32_t PHX_M0 = 0xD2511F53u;
+constexpr uint32_t PHX_M1 = 0xCD9E8D57u;
+constexpr uint32_t PHX_W0 = 0x9E3779B9u;
+constexpr uint32_t PHX_W1 = 0xBB67AE85u;
+
+__device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = PHX_M0 * c.x, hi0 = __umulhi(PHX_M0, c.x);
+        const uint32_t lo1 = PHX_M1 * c.z, hi1 = __umulhi(PHX_M1, c.z);
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        k0 += PHX_W0;
+        k1 += PHX_W1;
+    }
+    return c;
+}
+
+// ---------------------------------------------------------------------------
+// Extended-range weights: x = m * 2^e, m in [0.5, 1) (m = 0, e = 0 for zero).
+// Every operation is the correctly rounded result of the exact operation on
+// the represented values (frexp and ldexp by at most 63 binades are exact),
+// so weights of any size are carried without underflow or overflow.
+// ---------------------------------------------------------------------------
+struct XF {
+    double m;
+    int e;
+};
+
+__device__ __forceinline__ XF xf_norm(double x, int e) {
+    const double m = __builtin_amdgcn_frexp_mant(x);
+    const int k = __builtin_amdgcn_frexp_exp(x);
+    XF r;
+    r.m = m;
+    r.e = (m == 0.0) ? 0 : e + k;
+    return r;
+}
+
+__device__ __forceinline__ XF xf_add(XF a, XF b) {
+    if (a.m == 0.0) return b;
+    if (b.m == 0.0) return a;
+    if (a.e < b.e) { const XF t = a; a = b; b = t; }
+    const int d = a.e - b.e;
+    if (d > 63) return a;
+    return xf_norm(a.m + ldexp(b.m, -d), a.e);
+}
+
+__device__ __forceinline__ XF xf_mul(XF a, double k) { return xf_norm(a.m * k, a.e); }
+__device__ __forceinline__ XF xf_div(XF a, double k) { return xf_norm(a.m / k, a.e); }
+
+// a / b as an ordinary double, exponent gap clamped to [-1000, 1000].
+__device__ __forceinline__ double xf_ratio(XF a, XF b) {
+    if (a.m == 0.0) return 0.0;
+    const int d = a.e - b.e;
+    if (d < -1000) return 0.0;
+    if (d > 1000) return 0x1p1000;
+    return ldexp(a.m / b.m, d);
+}
+
+__device__ __forceinline__ XF xf_of(const SumRec& r) { return XF{r.m, r.e}; }
+
+// ---------------------------------------------------------------------------
+// Lattice: packed int16 coordinates (offset by 2^15 so that key 0 never
+// occurs and marks an empty slot), direction order +x,-x,+y,-y,+z,-z.
+// ---------------------------------------------------------------------------
+template <int D> struct Lat;
+template <> struct Lat<2> {
+    using Key = uint32_t;
+    static constexpr int DP = 4;  // direction lanes per probe window
+    __device__ static Key pack(int x, int y, int) {
+        return (uint32_t)(x + 32768) | ((uint32_t)(y + 32768) << 16);
+    }
+    __device__ static void unpack(Key k, int& x, int& y, int& z) {
+        x = (int)(k & 0xFFFFu) - 32768;
+        y = (int)(k >> 16) - 32768;
+        z = 0;
+    }
+    __device__ static uint32_t hash(Key k) { return k * 0x9E3779B1u; }
+};
+template <> struct Lat<3> {
+    using Key = uint64_t;
+    static constexpr int DP = 8;
+    __device__ static Key pack(int x, int y, int z) {
+        return (uint64_t)(uint32_t)(x + 32768) | ((uint64_t)(uint32_t)(y + 32768) << 16) |
+               ((uint64_t)(uint32_t)(z + 32768) << 32);
+    }
+    __device__ static void unpack(Key k, int& x, int& y, int& z) {
+        x = (int)(k & 0xFFFFu) - 32768;
+        y = (int)((k >> 16) & 0xFFFFu) - 32768;
+        z = (int)((k >> 32) & 0xFFFFu) - 32768;
+    }
+    __device__ static uint32_t hash(Key k) {
+        return (uint32_t)k * 0x9E3779B1u + (uint32_t)(k >> 32) * 0x85EBCA77u;
+    }
+};
+
+__device__ __forceinline__ int dir_dx(int d) { return (d == 0) - (d == 1); }
+__device__ __forceinline__ int dir_dy(int d) { return (d == 2) - (d == 3); }
+__device__ __forceinline__ int dir_dz(int d) { return (d == 4) - (d == 5); }
+
+__device__ __forceinline__ void wave_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Team phases.
+enum : int { PH_NEED_SEQ = 0, PH_NEED_TOUR = 1, PH_NEED_BT = 2, PH_AT_NODE = 3, PH_DONE = 4,
+             PH_ABORT = 5 };
+
+constexpr uint64_t FNV_PRIME = 0x00000100000001B3ull;
+
+// Bits 0, DP, 2*DP, ... (W of them): the lanes of one direction in a team.
+template <int DP, int W>
+__device__ __forceinline__ uint64_t dir_rep() {
+    uint64_t r = 0;
+#pragma unroll
+    for (int j = 0; j < W; ++j) r |= 1ull << (j * DP);
+    return r;
+}
+
+// Fold a team-local lane mask (TS bits) onto direction bits (DP bits).
+template <int TS, int DP>
+__device__ __forceinline__ uint32_t fold_dirs(uint64_t x) {
+#pragma unroll
+    for (int s = TS / 2; s >= DP; s /= 2) x |= x >> s;
+    return (uint32_t)(x & ((1u << DP) - 1u));
+}
+
+template <int D, int TS>
+__global__ void __launch_bounds__(64) run_kernel(RunArgs A) {
+    using L_ = Lat<D>;
+    using Key = typename L_::Key;
+    constexpr int DP = L_::DP;
+    static_assert(TS >= DP && TS <= 64 && (TS & (TS - 1)) == 0, "team size");
+    constexpr int W = TS / DP;          // probe positions per direction per round
+    constexpr int TPW = 64 / TS;        // teams per wave
+
+    extern __shared__ __align__(16) unsigned char lds[];
+    const int lane = (int)threadIdx.x;
+    const int lt = lane & (TS - 1);
+    const int tbase = lane & ~(TS - 1);
+    const int tiw = lane / TS;
+    const uint32_t team_slot = blockIdx.x * TPW + tiw;
+
+    Key* table = reinterpret_cast<Key*>(lds + (size_t)tiw * A.lds_team_bytes);
+    uint16_t* sid = reinterpret_cast<uint16_t*>(lds + (size_t)tiw * A.lds_team_bytes +
+                                                (sizeof(Key) << A.slots_log2));
+    const uint32_t S = 1u << A.slots_log2;
+    const uint32_t smask = S - 1u;
+    const uint32_t hshift = 32u - A.slots_log2;
+
+    // probe-lane role
+    const int pdir = lt % DP;
+    const int poff = lt / DP;
+    const bool pvalid = pdir < 2 * D;
+    const int pdx = dir_dx(pdir), pdy = dir_dy(pdir), pdz = dir_dz(pdir);
+    const uint64_t same_dir = dir_rep<DP, W>() << (tbase + pdir);
+    const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    const uint64_t same_dir_below = same_dir & below;
+
+    const uint32_t n_max = A.n_max;
+    const uint32_t row = A.row;
+    const bool shared_mode = (A.mode == MODE_SHARED);
+    const bool control_mode = (A.mode != MODE_ROSENBLUTH);
+    // in Algorithm 2 a sequence's own epoch data stands for the pool's: weight N
+    const double pool = shared_mode ? (double)A.N : 1.0;
+    const uint64_t pool_u = shared_mode ? (uint64_t)A.N : 1ull;
+    const uint32_t cap = A.step_cap;
+
+    // empty table with the origin in it; slot id of site 0
+    for (uint32_t i = (uint32_t)lt; i < S; i += TS) table[i] = (Key)0;
+    wave_fence();
+    const Key origin_key = L_::pack(0, 0, 0);
+    if (lt == 0) {
+        const uint32_t h = L_::hash(origin_key) >> hshift;
+        table[h] = origin_key;
+        sid[0] = (uint16_t)h;
+    }
+    wave_fence();
+
+    StackEntry* stk = A.stack + (size_t)team_slot * n_max;
+
+    // ---- team state (identical in every lane of a team) ----
+    int phase = PH_NEED_SEQ;
+    uint32_t s = 0, tours_left = 0, m = 0;
+    uint64_t t = 0, tt = 0;
+    SumRec rec0 = {0.0, 0, 0u};           // L[s][0]: one record per tour
+    const SumRec* Grow = A.G;
+    uint64_t MGs = shared_mode ? A.MG[0] : 0;
+    uint64_t st_steps = 0, st_events = 0, st_enrich = 0, st_copies = 0, st_prunes = 0,
+             st_traps = 0, st_tours = 0, st_maxd = 0, st_digest = 0, st_capped = 0;
+    uint32_t steps_call = 0;
+
+    uint32_t n = 0;
+    XF w = {0.5, 1};
+    int ex = 0, ey = 0, ez = 0;
+    bool control = false;
+    uint64_t k = 0, kb = 0;
+    bool stale = true;
+    uint4 rb = make_uint4(0, 0, 0, 0);
+
+    uint32_t sp = 0, top_n = 0, top_rem = 0;
+    XF top_w = {0.0, 0};
+
+    SumRec Lp = {0.0, 0, 0u}, Gp = {0.0, 0, 0u};   // records of length n + 1 (prefetched)
+    XF Lc = {0.0, 0}, Gc = {0.0, 0};               // sums at length n after its record
+
+    for (;;) {
+        // ---------------- (1) acquire a sequence ----------------
+        const bool need_seq = (phase == PH_NEED_SEQ);
+        uint32_t got = 0xFFFFFFFFu;
+        if (need_seq && lt == 0) got = atomicAdd(&A.ctrl[CTRL_QUEUE], 1u);
+        got = __shfl(got, tbase, 64);
+        if (need_seq) {
+            if (got < A.N) {
+                s = got;
+                const size_t rb0 = (size_t)s * row;
+                t = A.t[s];
+                m = A.m[s];
+                rec0 = A.L[rb0];
+                const uint64_t* sr = A.stats + (size_t)s * STATS_WORDS;
+                st_steps = sr[ST_STEPS]; st_events = sr[ST_EVENTS]; st_enrich = sr[ST_ENRICH];
+                st_copies = sr[ST_COPIES]; st_prunes = sr[ST_PRUNES]; st_traps = sr[ST_TRAPS];
+                st_tours = sr[ST_TOURS]; st_maxd = sr[ST_MAXDEPTH]; st_digest = sr[ST_DIGEST];
+                st_capped = sr[ST_CAPPED];
+                if (!shared_mode) {
+                    Grow = A.G + rb0;
+                    MGs = A.MG[s];
+                }
+                tours_left = A.tours;
+                steps_call = 0;
+                phase = PH_NEED_TOUR;
+            } else {
+                phase = PH_DONE;
+            }
+        }
+        if (__ballot(phase != PH_DONE) == 0ull) break;
+
+        SumRec* Lrow = A.L + (size_t)s * row;
+
+        // ---------------- (2) backtrack / end of tour ----------------
+        if (phase == PH_NEED_BT || phase == PH_ABORT) {
+            const bool abort = (phase == PH_ABORT);
+            const bool tour_end = abort || sp == 0;
+            uint32_t rn = 0;
+            if (!tour_end) {
+                rn = top_n;
+                w = top_w;
+                top_rem -= 1;
+                if (top_rem == 0) {
+                    sp -= 1;
+                    if (sp > 0) {
+                        const StackEntry e = stk[sp - 1];
+                        top_n = e.n;
+                        top_rem = e.remaining;
+                        top_w = XF{e.m, e.e};
+                    }
+                }
+            }
+            // LIFO deletion of sites rn+1..n restores the table exactly
+            for (uint32_t i = rn + 1 + (uint32_t)lt; i <= n; i += TS) table[sid[i]] = (Key)0;
+            if (!tour_end) {
+                const Key ek = table[sid[rn]];
+                L_::unpack(ek, ex, ey, ez);
+                n = rn;
+                control = false;
+                phase = PH_AT_NODE;
+                Lp = Lrow[n + 1];
+                Gp = Grow[n + 1];
+            } else {
+                n = 0;
+                ex = ey = ez = 0;
+                sp = 0;
+                if (abort) {
+                    st_capped = 1;
+                    tours_left = 0;
+                    if (lt == 0) atomicOr(&A.ctrl[CTRL_ERR], ERR_CAP);
+                } else {
+                    tours_left -= 1;
+                }
+                if (tours_left > 0) {
+                    phase = PH_NEED_TOUR;
+                } else {
+                    if (lt == 0) {
+                        const size_t rb0 = (size_t)s * row;
+                        A.L[rb0] = rec0;
+                        A.t[s] = t;
+                        A.m[s] = m;
+                        uint64_t* sr = A.stats + (size_t)s * STATS_WORDS;
+                        sr[ST_STEPS] = st_steps; sr[ST_EVENTS] = st_events; sr[ST_ENRICH] = st_enrich;
+                        sr[ST_COPIES] = st_copies; sr[ST_PRUNES] = st_prunes; sr[ST_TRAPS] = st_traps;
+                        sr[ST_TOURS] = st_tours; sr[ST_MAXDEPTH] = st_maxd; sr[ST_DIGEST] = st_digest;
+                        sr[ST_CAPPED] = st_capped;
+                    }
+                    phase = PH_NEED_SEQ;
+                }
+            }
+        }
+
+        // ---------------- (3) start of a tour ----------------
+        if (phase == PH_NEED_TOUR) {
+            tt = t;
+            t += 1;
+            m += 1;
+            st_tours += 1;
+            w = XF{0.5, 1};                       // W_0 = 1
+            {
+                const XF r0 = xf_add(xf_of(rec0), w);
+                rec0.m = r0.m;
+                rec0.e = r0.e;
+                rec0.h += 1u;
+            }
+            k = 0;
+            stale = true;
+            n = 0;
+            ex = ey = ez = 0;
+            control = false;
+            phase = PH_AT_NODE;
+            Lp = Lrow[1];
+            Gp = Grow[1];
+        }
+        wave_fence();
+
+        // ---------------- (4) occupancy scan at the endpoint ----------------
+        const bool probing = (phase == PH_AT_NODE);
+        const Key nk = L_::pack(ex + pdx, ey + pdy, ez + pdz);
+        const uint32_t home = L_::hash(nk) >> hshift;
+        bool open = probing && pvalid;
+        uint32_t freem = 0;
+        int my_ins = -1;
+        uint32_t pos = home + (uint32_t)poff;
+        for (;;) {
+            if (__ballot(open) == 0ull) break;
+            bool hit = false, emp = false;
+            uint32_t slot = 0;
+            if (open) {
+                slot = pos & smask;
+                const Key v = table[slot];
+                hit = (v == nk);
+                emp = (v == (Key)0);
+            }
+            const bool res = hit || emp;
+            const uint64_t bres = __ballot(res);
+            const bool first = res && ((bres & same_dir_below) == 0ull);
+            const uint64_t bfe = __ballot(first && emp);
+            const uint64_t bfr = __ballot(first);
+            const uint64_t tmaskl = (TS == 64) ? ~0ull : ((1ull << TS) - 1ull);
+            freem |= fold_dirs<TS, DP>((bfe >> tbase) & tmaskl);
+            const uint32_t done_dirs = fold_dirs<TS, DP>((bfr >> tbase) & tmaskl);
+            if (first && emp) my_ins = (int)slot;
+            if ((done_dirs >> pdir) & 1u) open = false;
+            pos += W;
+        }
+        const uint32_t a = (uint32_t)__popc(freem);
+        if (probing && a == 0) {
+            st_traps += 1;
+            phase = PH_NEED_BT;
+        }
+
+        // ---------------- (5) random blocks ----------------
+        const bool growing = (phase == PH_AT_NODE);
+        if (__ballot(growing && (stale || (k - kb) >= (uint64_t)TS)) != 0ull) {
+            kb = k;
+            stale = false;
+            const uint64_t kk = kb + (uint64_t)lt;
+            rb = philox10(make_uint4((uint32_t)kk, (uint32_t)(kk >> 32), (uint32_t)tt, s), A.key0,
+                          A.key1);
+        }
+        const int src = tbase + (int)((uint32_t)(k - kb) & (uint32_t)(TS - 1));
+        const uint32_t B0 = __shfl(rb.x, src, 64);
+        const uint32_t B1 = __shfl(rb.y, src, 64);
+        const uint32_t B2 = __shfl(rb.z, src, 64);
+
+        // ---------------- (6) decision, growth, record ----------------
+        if (growing) {
+            k += 1;
+            st_events += 1;
+            bool pruned = false;
+            if (control) {
+                // eqn (6): r = W / [W_n], [W_n] = sum / seen with the sequence's
+                // own epoch data weighted N; evaluated as (W * seen) / sum
+                const XF sum = xf_add(Gc, xf_mul(Lc, pool));
+                const double seen = (double)(MGs + pool_u * (uint64_t)m);
+                const double r = xf_ratio(xf_mul(w, seen), sum);
+                const double u = ((double)(B1 >> 5) * 67108864.0 + (double)(B2 >> 6)) *
+                                 (1.0 / 9007199254740992.0);
+                if (r >= 1.0) {
+                    const double f = floor(r);
+                    double c;
+                    if (r != f && u < (f + 1.0) - r) c = f;
+                    else c = (r == f) ? f : f + 1.0;
+                    w = xf_div(w, c);
+                    if (c > 1.0) {
+                        const uint32_t ci = (uint32_t)c;
+                        if (sp > 0) {
+                            // every lane of the team stores (and later reloads) the
+                            // entry, so each lane only ever reads its own writes
+                            StackEntry e;
+                            e.n = top_n;
+                            e.remaining = top_rem;
+                            e.e = top_w.e;
+                            e.pad0 = 0u;
+                            e.m = top_w.m;
+                            e.pad1 = 0ull;
+                            stk[sp - 1] = e;
+                        }
+                        top_n = n;
+                        top_rem = ci - 1u;
+                        top_w = w;
+                        sp += 1;
+                        if ((uint64_t)sp > st_maxd) st_maxd = sp;
+                        st_enrich += 1;
+                        st_copies += (uint64_t)(ci - 1u);
+                    }
+                } else {
+                    // a survivor takes W / r, the running average itself
+                    if (u < r) w = xf_div(sum, seen);
+                    else pruned = true;
+                }
+            }
+            if (pruned) {
+                st_prunes += 1;
+                phase = PH_NEED_BT;
+            } else {
+                const uint32_t j = __umulhi(B0, a);
+                uint32_t mm = freem;
+                for (uint32_t i = 0; i < j; ++i) mm &= mm - 1u;
+                const int dir = __ffs(mm) - 1;
+                st_digest = (st_digest ^ (uint64_t)((uint32_t)dir | (a << 3))) * FNV_PRIME;
+                if (my_ins >= 0 && pdir == dir) {
+                    table[my_ins] = nk;
+                    sid[n + 1] = (uint16_t)my_ins;
+                }
+                ex += dir_dx(dir);
+                ey += dir_dy(dir);
+                ez += dir_dz(dir);
+                w = xf_mul(w, (double)a);      // W *= a_+, eqn (2)
+                if (w.e > EXP_LIMIT || w.e < -EXP_LIMIT) {
+                    if (lt == 0) atomicOr(&A.ctrl[CTRL_ERR], ERR_RANGE);
+                }
+                n += 1;
+                st_steps += 1;
+                steps_call += 1;
+                // arrival: record into the running sums (eqn (4))
+                const XF Lnew = xf_add(xf_of(Lp), w);
+                SumRec nr;
+                nr.m = Lnew.m;
+                nr.e = Lnew.e;
+                nr.h = Lp.h + 1u;
+                Lrow[n] = nr;
+                Lc = Lnew;
+                Gc = xf_of(Gp);
+                if (cap != 0u && steps_call >= cap) {
+                    phase = PH_ABORT;
+                } else if (n == n_max) {
+                    phase = PH_NEED_BT;
+                } else {
+                    control = control_mode;
+                    Lp = Lrow[n + 1];
+                    Gp = Grow[n + 1];
+                }
+            }
+        }
+        wave_fence();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Merge: aligned pairwise tree over sequences.  One wave takes 64 consecutive
+// rows (sequences) and a strip of 16 columns (lengths); lane i holds row i and
+// the tree over the 64 lanes is a butterfly of lane shuffles (xor 1, 2, ..,
+// 32): after level l every lane holds the sum of its aligned block of 2^(l+1)
+// rows, added as (left block) + (right block) up to commutativity, which IEEE
+// addition has.  Partial trees of aligned 64-row blocks are the tree's own
+// nodes, so repeated passes give the whole tree; missing rows are +0.0.
+// ---------------------------------------------------------------------------
+constexpr int MERGE_COLS = 8;
+
+__global__ void __launch_bounds__(64) merge_pass_kernel(MergeArgs A) {
+    const int lane = (int)threadIdx.x;
+    const uint32_t r = blockIdx.y * 64u + (uint32_t)lane;
+    const uint32_t c0 = blockIdx.x * MERGE_COLS;
+    XF v[MERGE_COLS];
+    uint64_t h[MERGE_COLS];
+    const bool rv = r < A.rows;
+#pragma unroll
+    for (int j = 0; j < MERGE_COLS; ++j) {
+        const uint32_t c = c0 + (uint32_t)j;
+        const bool ok = rv && c < A.ncols;
+        const size_t idx = (size_t)r * A.row + c;
+        SumRec rec = {0.0, 0, 0u};
+        if (ok) rec = A.in[idx];
+        v[j] = xf_of(rec);
+        h[j] = ok ? (A.hin ? A.hin[idx] : (uint64_t)rec.h) : 0ull;
+    }
+    if (A.zero && rv) {
+        const SumRec z = {0.0, 0, 0u};
+#pragma unroll
+        for (int j = 0; j < MERGE_COLS; ++j) {
+            const uint32_t c = c0 + (uint32_t)j;
+            if (c < A.ncols) A.zero[(size_t)r * A.row + c] = z;
+        }
+    }
+    // butterfly: after step lvl every lane holds the sum of its aligned block of
+    // 2*lvl rows; the extended-range sum is commutative, so both lanes of a pair
+    // compute the same (left block) + (right block)
+#pragma unroll
+    for (int lvl = 1; lvl < 64; lvl <<= 1) {
+#pragma unroll
+        for (int j = 0; j < MERGE_COLS; ++j) {
+            XF o;
+            o.m = __shfl_xor(v[j].m, lvl, 64);
+            o.e = __shfl_xor(v[j].e, lvl, 64);
+            v[j] = xf_add(v[j], o);
+            h[j] += __shfl_xor(h[j], lvl, 64);
+        }
+    }
+    if (lane < MERGE_COLS) {
+        // select column `lane` without dynamic register indexing
+        XF vv = {0.0, 0};
+        uint64_t hh = 0;
+#pragma unroll
+        for (int j = 0; j < MERGE_COLS; ++j) {
+            if (j == lane) { vv = v[j]; hh = h[j]; }
+        }
+        const uint32_t c = c0 + (uint32_t)lane;
+        if (c < A.ncols) {
+            const size_t o = (size_t)blockIdx.y * A.row + c;
+            if (A.accumulate) {
+                vv = xf_add(xf_of(A.out[o]), vv);
+                hh += A.hout[o];
+            }
+            SumRec rec;
+            rec.m = vv.m;
+            rec.e = vv.e;
+            rec.h = 0u;
+            A.out[o] = rec;
+            A.hout[o] = hh;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) merge_counts_kernel(const uint32_t* m, uint32_t N,
+                                                           uint64_t* MG, uint32_t* zero_m) {
+    // one block: exact integer sum of the per-sequence tour counts
+    __shared__ uint64_t part[256];
+    uint64_t acc = 0;
+    for (uint32_t i = threadIdx.x; i < N; i += 256) acc += m[i];
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < N; i += 256) zero_m[i] = 0u;
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) part[threadIdx.x] += part[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) MG[0] += part[0];
+}
+
+__global__ void __launch_bounds__(256) merge_independent_kernel(SumRec* L, uint32_t* m, SumRec* G,
+                                                                uint64_t* HG, uint64_t* MG,
+                                                                uint32_t N, uint32_t row) {
+    const size_t total = (size_t)N * row;
+    const SumRec z = {0.0, 0, 0u};
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * 256) {
+        const SumRec l = L[i];
+        const XF g = xf_add(xf_of(G[i]), xf_of(l));
+        SumRec rec;
+        rec.m = g.m;
+        rec.e = g.e;
+        rec.h = 0u;
+        G[i] = rec;
+        HG[i] += l.h;
+        L[i] = z;
+    }
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (size_t)gridDim.x * 256) {
+        MG[i] += m[i];
+        m[i] = 0u;
+    }
+}
+
+__global__ void reset_ctrl_kernel(uint32_t* ctrl) {
+    if (threadIdx.x == CTRL_QUEUE) ctrl[CTRL_QUEUE] = 0u;
+}
+
+__global__ void __launch_bounds__(256) init_state_kernel(uint64_t* stats, uint32_t N,
+                                                         uint32_t* zero, size_t words) {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < words;
+         i += (size_t)gridDim.x * 256)
+        zero[i] = 0u;
+    // stats rows: counters 0, digest = FNV-1a offset basis
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (size_t)gridDim.x * 256)
+        stats[i * STATS_WORDS + ST_DIGEST] = 0xCBF29CE484222325ull;
+}
+
+template <int D, int TS>
+hipError_t launch_run_t(const RunArgs& a, uint32_t wgs, uint32_t lds, hipStream_t s) {
+    hipLaunchKernelGGL((run_kernel<D, TS>), dim3(wgs), dim3(64), lds, s, a);
+    return hipGetLastError();
+}
+
+template <int D, int TS>
+hipError_t occupancy_t(uint32_t lds, int* blocks) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, run_kernel<D, TS>, 64, lds);
+}
+
+}  // namespace
+
+hipError_t launch_reset_ctrl(uint32_t* ctrl, hipStream_t s) {
+    hipLaunchKernelGGL(reset_ctrl_kernel, dim3(1), dim3(64), 0, s, ctrl);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_state(uint64_t* stats, uint32_t N, void* zero_base, size_t zero_bytes,
+                             hipStream_t s) {
+    // zero everything first, then the digest seeds: same kernel, in order
+    const size_t words = zero_bytes / 4;
+    uint32_t blocks = (uint32_t)((words + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    if (blocks == 0) blocks = 1;
+    hipLaunchKernelGGL(init_state_kernel, dim3(blocks), dim3(256), 0, s, (uint64_t*)nullptr, 0u,
+                       (uint32_t*)zero_base, words);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(init_state_kernel, dim3((N + 255) / 256), dim3(256), 0, s, stats, N,
+                       (uint32_t*)nullptr, (size_t)0);
+    return hipGetLastError();
+}
+
+#define PPERM_TS_SWITCH(D, FN, ...)                                     \
+    switch (team_lanes) {                                               \
+        case 4: if (D == 2) return FN<2, 4>(__VA_ARGS__); break;        \
+        case 8: return FN<D, 8>(__VA_ARGS__);                           \
+        case 16: return FN<D, 16>(__VA_ARGS__);                         \
+        case 32: return FN<D, 32>(__VA_ARGS__);                         \
+        case 64: return FN<D, 64>(__VA_ARGS__);                         \
+        default: break;                                                 \
+    }
+
+hipError_t launch_run(const RunArgs& a, uint32_t dim, uint32_t team_lanes, uint32_t workgroups,
+                      uint32_t lds_bytes, hipStream_t s) {
+    if (dim == 2) {
+        PPERM_TS_SWITCH(2, launch_run_t, a, workgroups, lds_bytes, s)
+    } else if (dim == 3) {
+        PPERM_TS_SWITCH(3, launch_run_t, a, workgroups, lds_bytes, s)
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t run_kernel_lds_ok(uint32_t dim, uint32_t team_lanes, uint32_t lds_bytes,
+                             int* blocks_per_cu) {
+    if (dim == 2) {
+        PPERM_TS_SWITCH(2, occupancy_t, lds_bytes, blocks_per_cu)
+    } else if (dim == 3) {
+        PPERM_TS_SWITCH(3, occupancy_t, lds_bytes, blocks_per_cu)
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_merge_pass(const MergeArgs& a, hipStream_t s) {
+    dim3 grid((a.ncols + MERGE_COLS - 1) / MERGE_COLS, (a.rows + 63) / 64);
+    hipLaunchKernelGGL(merge_pass_kernel, grid, dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_merge_counts(const uint32_t* m, uint32_t N, uint64_t* MG, uint32_t* zero_m,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(merge_counts_kernel, dim3(1), dim3(256), 0, s, m, N, MG, zero_m);
+    return hipGetLastError();
+}
+
+hipError_t launch_merge_independent(SumRec* L, uint32_t* m, SumRec* G, uint64_t* HG, uint64_t* MG,
+                                    uint32_t N, uint32_t row, hipStream_t s) {
+    size_t total = (size_t)N * row;
+    uint32_t blocks = (uint32_t)((total + 255) / 256);
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(merge_independent_kernel, dim3(blocks), dim3(256), 0, s, L, m, G, HG, MG,
+                       N, row);
+    return hipGetLastError();
+}
+
+}  // namespace pperm

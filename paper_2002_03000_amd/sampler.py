@@ -1,0 +1,124 @@
+"""Python face of libpperm: one parallel flatPERM problem on one GPU.
+
+Device memory and the stream come from torch; every step of the method runs
+in the library's HIP kernels.  This class only marshals arguments.
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _abi
+
+
+class ParallelFlatPERM:
+    """N interacting flatPERM sequences growing SAWs on Z^dim (Algorithm 2 by default).
+
+    mode: "shared" (Algorithm 2), "independent" (Algorithm 1) or "rosenbluth".
+    hash_slots / walks_per_wave: launch tuning, 0 = automatic; they never change results.
+    """
+
+    def __init__(self, dim, n_max, n_sequences, seed, mode="shared", stream_id=0,
+                 hash_slots=0, walks_per_wave=0, step_cap=0, device=None, stream=None):
+        lib = _abi.load()
+        self.cfg = _abi.Config(ctypes.sizeof(_abi.Config), dim, n_max, n_sequences,
+                               seed & 0xFFFFFFFFFFFFFFFF, _abi.MODES[mode], stream_id,
+                               hash_slots, walks_per_wave, step_cap, 0)
+        self.dim, self.n_max, self.N, self.mode = dim, n_max, n_sequences, mode
+        self.device = torch.device(device if device is not None else "cuda")
+        nbytes = ctypes.c_size_t()
+        _abi.check(lib.pperm_workspace_bytes(ctypes.byref(self.cfg), ctypes.byref(nbytes)),
+                   "pperm_workspace_bytes")
+        self.workspace_bytes = int(nbytes.value)
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+            ctx = ctypes.c_void_p()
+            _abi.check(lib.pperm_create(ctypes.byref(self.cfg), ctypes.c_void_p(self.workspace.data_ptr()),
+                                        self.workspace_bytes, ctypes.c_void_p(self.stream.cuda_stream),
+                                        ctypes.byref(ctx)), "pperm_create")
+        self._ctx = ctx
+        self._lib = lib
+        lay = _abi.Layout()
+        _abi.check(lib.pperm_layout_of(self._ctx, ctypes.byref(lay)), "pperm_layout_of")
+        self.layout = lay
+
+    # -- the four calls of the method -------------------------------------------------
+    def run_tours(self, tours_per_sequence):
+        _abi.check(self._lib.pperm_run_tours(self._ctx, int(tours_per_sequence)), "pperm_run_tours")
+
+    def merge_epoch(self):
+        _abi.check(self._lib.pperm_merge_epoch(self._ctx), "pperm_merge_epoch")
+
+    def estimates(self):
+        """(log c_n estimates, samples per length, pooled tour count) of the merged state."""
+        n1 = self.n_max + 1
+        lc = np.zeros(n1, dtype=np.float64)
+        hist = np.zeros(n1, dtype=np.uint64)
+        tours = ctypes.c_uint64()
+        _abi.check(self._lib.pperm_estimates(self._ctx, lc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                             hist.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                             ctypes.byref(tours), n1), "pperm_estimates")
+        return lc, hist, int(tours.value)
+
+    # -- inspection -------------------------------------------------------------------
+    def sync(self):
+        _abi.check(self._lib.pperm_sync(self._ctx), "pperm_sync")
+
+    def sequence_stats(self):
+        arr = (_abi.SeqStats * self.N)()
+        _abi.check(self._lib.pperm_sequence_stats(self._ctx, arr, self.N), "pperm_sequence_stats")
+        dt = np.dtype([(f, np.uint64) for f in _abi.STATS_FIELDS])
+        return np.frombuffer(bytes(arr), dtype=dt).copy()
+
+    def stats(self):
+        tot = _abi.SeqStats()
+        _abi.check(self._lib.pperm_stats(self._ctx, ctypes.byref(tot)), "pperm_stats")
+        return {f: int(getattr(tot, f)) for f in _abi.STATS_FIELDS}
+
+    def launch_shape(self):
+        w, h, g = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+        _abi.check(self._lib.pperm_launch_shape(self._ctx, ctypes.byref(w), ctypes.byref(h), ctypes.byref(g)),
+                   "pperm_launch_shape")
+        return {"walks_per_wave": w.value, "hash_slots": h.value, "workgroups": g.value}
+
+    # 16-byte sum record: value = m * 2^e, h = sample count (0 in pooled sums)
+    RECORD_DTYPE = np.dtype([("m", np.float64), ("e", np.int32), ("h", np.uint32)])
+
+    def view(self, name):
+        """A torch view of one state array inside the workspace.
+
+        G and L hold 16-byte records (view them as uint8 and use `records`);
+        HG, MG, m, t and stats are plain integer arrays."""
+        lay = self.layout
+        row, N = lay.row, self.N
+        indep = self.mode == "independent"
+        shapes = {
+            "G": (torch.uint8, (N, row, 16) if indep else (row, 16)),
+            "HG": (torch.int64, (N, row) if indep else (row,)),
+            "MG": (torch.int64, (N,) if indep else (1,)),
+            "L": (torch.uint8, (N, row, 16)),
+            "m": (torch.int32, (N,)),
+            "t": (torch.int64, (N,)),
+            "stats": (torch.int64, (N, len(_abi.STATS_FIELDS))),
+        }
+        dt, shape = shapes[name]
+        off = getattr(lay, name)
+        nbytes = int(np.prod(shape)) * torch.tensor([], dtype=dt).element_size()
+        return self.workspace[off:off + nbytes].view(dt).view(shape)
+
+    def records(self, name):
+        """Host copy of the G or L records as a structured numpy array (m, e, h)."""
+        raw = self.view(name).cpu().numpy()
+        return raw.reshape(raw.shape[:-1] + (16,)).view(self.RECORD_DTYPE)[..., 0]
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            self._lib.pperm_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,80 @@
+"""The C ABI library loads on any host and exports what include/pperm.h declares.
+
+No compute is launched here (no GPU needed): configuration validation and
+workspace sizing are host-only calls.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2002_03000_amd import _abi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "pperm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pperm_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_method_calls():
+    names = _declared()
+    for n in ("pperm_create", "pperm_run_tours", "pperm_merge_epoch", "pperm_estimates"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _abi.load()
+    for name in _declared():
+        assert hasattr(lib, name), name
+    assert set(_declared()) == set(_abi.SIGNATURES)
+
+
+def _cfg(**kw):
+    d = dict(dim=2, n_max=100, n_sequences=64, seed=1, mode=0, stream_id=0, hash_slots=0,
+             walks_per_wave=0, step_cap=0, flags=0)
+    d.update(kw)
+    return _abi.Config(ctypes.sizeof(_abi.Config), d["dim"], d["n_max"], d["n_sequences"], d["seed"],
+                       d["mode"], d["stream_id"], d["hash_slots"], d["walks_per_wave"], d["step_cap"],
+                       d["flags"])
+
+
+def _ws(cfg):
+    n = ctypes.c_size_t()
+    rc = _abi.load().pperm_workspace_bytes(ctypes.byref(cfg), ctypes.byref(n))
+    return rc, n.value
+
+
+@pytest.mark.parametrize("bad", [dict(dim=1), dict(dim=4), dict(n_max=0), dict(n_max=32767),
+                                 dict(n_sequences=0), dict(mode=3), dict(flags=1),
+                                 dict(hash_slots=100), dict(hash_slots=128, n_max=100),
+                                 dict(walks_per_wave=3), dict(walks_per_wave=32),
+                                 dict(dim=3, walks_per_wave=16)])
+def test_invalid_configurations_are_rejected(bad):
+    rc, _ = _ws(_cfg(**bad))
+    assert rc == -1
+
+
+def test_struct_size_guards_the_abi():
+    c = _cfg()
+    c.struct_size = 8
+    assert _ws(c)[0] == -1
+
+
+@pytest.mark.parametrize("dim,n_max,N", [(2, 20, 1), (2, 500, 4096), (3, 1000, 16384), (3, 1500, 1024)])
+def test_workspace_sizes(dim, n_max, N):
+    rc, n = _ws(_cfg(dim=dim, n_max=n_max, n_sequences=N))
+    assert rc == 0
+    row = (n_max + 1 + 15) // 16 * 16
+    # at least the per-sequence sums (f64 + u32), pooled sums and the copy stacks
+    assert n >= N * row * 12 + N * n_max * 16
+    assert n % 256 == 0
+
+
+def test_strerror_covers_every_code():
+    lib = _abi.load()
+    for code in _abi.ERRORS:
+        assert lib.pperm_strerror(code).decode() != "unknown error"

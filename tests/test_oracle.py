@@ -70,14 +70,63 @@ def test_forced_choice_drive_counts_every_walk_once(dim, n_max):
     assert [int(x) for x in cnt] == [SAW[dim][n] for n in range(n_max + 1)]
 
 
-def test_scaled_exponent_tracks_growth_constant():
-    # E_n = floor(n log2 mu_d) in 32.32 fixed point; mu_d from Sec. 3.3.
-    for d, mu in ((2, 2.63815853035), (3, 4.684039931)):
-        for n in (0, 1, 2, 3, 10, 500, 1000, 2048, 32767):
-            e = oracle.scale_exponent(d, n)
-            assert e == math.floor(n * math.log2(mu)) or abs(n * math.log2(mu) - round(n * math.log2(mu))) < 1e-6
-            assert abs(e - n * math.log2(mu)) <= 1.0
-    assert oracle.weight_step(2, 1.0, 4, 0) == 4.0 / 2 ** oracle.scale_exponent(2, 1)
+def _xf_exact(m, e):
+    from fractions import Fraction
+    return Fraction(float(m)) * (Fraction(2) ** int(e))
+
+
+def _round_xf(x):
+    """Correctly rounded extended-range number (m in [0.5, 1), e) of a Fraction."""
+    from fractions import Fraction
+    if x == 0:
+        return 0.0, 0
+    k = x.numerator.bit_length() - x.denominator.bit_length()
+    while x / (Fraction(2) ** k) >= 1:
+        k += 1
+    while x / (Fraction(2) ** k) < Fraction(1, 2):
+        k -= 1
+    m = float(x / (Fraction(2) ** k))     # Fraction -> float rounds to nearest even
+    if m == 1.0:
+        m, k = 0.5, k + 1
+    return m, k
+
+
+@pytest.mark.parametrize("op", ["add", "mul", "div"])
+def test_extended_range_operations_are_correctly_rounded(op):
+    # Weights are m * 2^e with an FP64 mantissa; every operation must equal the
+    # exact operation on the represented values, rounded to 53 bits.
+    rng = np.random.default_rng({"add": 1, "mul": 2, "div": 3}[op])
+    n = 3000
+    am, ae = oracle.xf_from_float(rng.uniform(0.5, 1.0, n))
+    ae = ae + rng.integers(-3000, 3000, n).astype(np.int32)
+    bm, be = oracle.xf_from_float(rng.uniform(0.5, 1.0, n))
+    # exponent gaps from 0 to beyond the 63-binade cut-off, both signs
+    be = ae + rng.integers(-90, 90, n).astype(np.int32)
+    be[:50] = ae[:50]
+    k = rng.integers(1, 2 ** 32, n).astype(np.float64)
+    k[:100] = rng.integers(1, 7, 100)
+    om, oe = oracle.xf_apply(op, am, ae, bm, be, k)
+    for i in range(n):
+        a = _xf_exact(am[i], ae[i])
+        if op == "add":
+            x = a + _xf_exact(bm[i], be[i])
+        elif op == "mul":
+            x = a * int(k[i])
+        else:
+            from fractions import Fraction
+            x = a / Fraction(int(k[i]))
+        assert (om[i], int(oe[i])) == _round_xf(x), (op, i)
+
+
+def test_extended_range_zero_and_ratio():
+    om, oe = oracle.xf_apply("add", [0.0], [0], [0.75], [12])
+    assert (om[0], oe[0]) == (0.75, 12)
+    om, oe = oracle.xf_apply("add", [0.75], [12], [0.0], [0])
+    assert (om[0], oe[0]) == (0.75, 12)
+    # ratio: ordinary double of a / b, exponent gap clamped at +-1000
+    assert oracle.xf_ratio(0.75, 10, 0.5, 9) == 3.0
+    assert oracle.xf_ratio(0.5, -5000, 0.5, 0) == 0.0
+    assert oracle.xf_ratio(0.0, 0, 0.5, 3) == 0.0
 
 
 # --------------------------------------------------------------------------
@@ -165,9 +214,13 @@ def test_occupancy_set_against_python_set():
 # --------------------------------------------------------------------------
 
 def _cn_hat(o):
-    n = np.arange(o.n_max + 1)
-    e = np.array([oracle.scale_exponent(o.dim, int(k)) for k in n], dtype=np.float64)
-    return o.G / float(o.MG[0]) * np.exp2(e)
+    return np.exp(oracle.xf_log(o.G) - np.log(float(o.MG[0])))
+
+
+def _cn_exact_ratio(o, n):
+    """G_n / M_G as an exact rational."""
+    from fractions import Fraction
+    return _xf_exact(o.G["m"][n], o.G["e"][n]) / Fraction(int(o.MG[0]))
 
 
 @pytest.mark.parametrize("dim", [2, 3])
@@ -180,10 +233,11 @@ def test_lengths_up_to_three_are_exact(dim, N, T, epochs, seed):
     for _ in range(epochs):
         assert o.run_tours(T) is False
         o.merge_epoch()
-    c = _cn_hat(o)
     q = 2 * dim
-    assert c[0] == 1.0
-    assert c[1] == q and c[2] == q * (q - 1) and c[3] == q * (q - 1) ** 2
+    assert _cn_exact_ratio(o, 0) == 1
+    assert _cn_exact_ratio(o, 1) == q
+    assert _cn_exact_ratio(o, 2) == q * (q - 1)
+    assert _cn_exact_ratio(o, 3) == q * (q - 1) ** 2
     assert int(o.MG[0]) == N * T * epochs
     assert int(o.HG[0]) == N * T * epochs
 
@@ -197,7 +251,8 @@ def test_first_tour_is_a_rosenbluth_walk(dim, seed):
     assert a.run_tours(1) is False
     b = oracle.Oracle(dim, 60, 1, seed, mode=oracle.MODE_ROSENBLUTH)
     b.run_tours(1)
-    assert np.array_equal(a.L, b.L) and np.array_equal(a.H, b.H)
+    assert np.array_equal(a.L["m"], b.L["m"]) and np.array_equal(a.L["e"], b.L["e"])
+    assert np.array_equal(a.H, b.H)
     assert a.stats["enrich"][0] == 0 and a.stats["prunes"][0] == 0
     assert a.stats["digest"][0] == b.stats["digest"][0]
 
@@ -207,7 +262,7 @@ def test_iterative_matches_recursive_description(dim, n_max, seed, tours):
     o = oracle.Oracle(dim, n_max, 1, seed)
     o.run_tours(tours)
     L, H = oracle.plain_recursive(dim, n_max, seed, tours)
-    assert np.array_equal(o.L[0], L)
+    assert np.array_equal(o.L[0]["m"], L["m"]) and np.array_equal(o.L[0]["e"], L["e"])
     assert np.array_equal(o.H[0], H)
 
 
@@ -218,25 +273,30 @@ def test_thread_count_does_not_change_results():
         for _ in range(2):
             o.run_tours(5)
             o.merge_epoch()
-        runs.append((o.G.copy(), o.HG.copy(), o.stats.copy()))
-    for g, h, s in runs[1:]:
-        assert np.array_equal(g, runs[0][0]) and np.array_equal(h, runs[0][1])
-        assert np.array_equal(s, runs[0][2])
+        runs.append((o.G["m"].copy(), o.G["e"].copy(), o.HG.copy(), o.stats.copy()))
+    for gm, ge, h, s in runs[1:]:
+        assert np.array_equal(gm, runs[0][0]) and np.array_equal(ge, runs[0][1])
+        assert np.array_equal(h, runs[0][2])
+        assert np.array_equal(s, runs[0][3])
 
 
 def test_merge_is_the_aligned_pairwise_tree():
-    # Values chosen so that the summation order is visible in the rounding.
+    # Values chosen so that the summation order is visible in the rounding:
+    # 2^53 + 1 + 1 + 1 + 1 summed as the tree over 8 leaves (3 of them +0).
     o = oracle.Oracle(2, 2, 5, 1)
-    big = 2.0 ** 53
-    o.L[:, 1] = [big, 1.0, 1.0, 1.0, 1.0]
+    vals = [2.0 ** 53, 1.0, 1.0, 1.0, 1.0]
+    m, e = oracle.xf_from_float(vals)
+    o.L["m"][:, 1] = m
+    o.L["e"][:, 1] = e
     o.m[:] = 1
     o.merge_epoch()
-    # tree over 8 leaves: (((b+1)+(1+1)) + ((1+0)+(0+0)))
+    big = 2.0 ** 53
     want = ((big + 1.0) + (1.0 + 1.0)) + ((1.0 + 0.0) + (0.0 + 0.0))
-    assert o.G[1] == want
-    assert o.G[1] != (((big + 1.0) + 1.0) + 1.0) + 1.0
+    got = math.ldexp(o.G["m"][1], int(o.G["e"][1]))
+    assert got == want
+    assert got != (((big + 1.0) + 1.0) + 1.0) + 1.0
     assert int(o.MG[0]) == 5
-    assert not o.L.any() and not o.H.any() and not o.m.any()
+    assert not o.L["m"].any() and not o.H.any() and not o.m.any()
 
 
 def test_step_cap_stops_a_sequence():
@@ -257,12 +317,7 @@ def _replicas(dim, n_max, N, T, epochs, seeds, mode=oracle.MODE_SHARED):
         for _ in range(epochs):
             o.run_tours(T)
             o.merge_epoch()
-        if mode == oracle.MODE_INDEPENDENT:
-            n = np.arange(n_max + 1)
-            e = np.exp2([oracle.scale_exponent(dim, int(k)) for k in n])
-            est.append(((o.G / o.MG[:, None].astype(float)) * e).mean(axis=0))
-        else:
-            est.append(_cn_hat(o))
+        est.append(np.exp(o.log_estimates()))
     return np.array(est)
 
 
@@ -280,7 +335,10 @@ def test_sample_average_is_unbiased(case):
     exact = _exact(case["dim"], case["n_max"])
     mean = est.mean(axis=0)
     se = est.std(axis=0, ddof=1) / math.sqrt(len(seeds))
-    z = np.where(se > 0, (mean - exact) / np.where(se > 0, se, 1.0), 0.0)
+    # lengths whose estimate does not vary between seeds are exact (n <= 3)
+    fixed = se < 1e-12 * exact
+    assert np.all(np.abs(mean[fixed] / exact[fixed] - 1.0) < 1e-12)
+    z = (mean - exact)[~fixed] / se[~fixed]
     assert np.all(np.abs(z) < 4.5), z
     # and the pooled estimate is close in relative terms
     assert np.all(np.abs(mean / exact - 1.0) < 0.02)
@@ -295,6 +353,7 @@ def test_plain_flatperm_c1_budget():
     c = _cn_hat(o)
     exact = _exact(2, 20)
     assert np.all(np.abs(c / exact - 1.0) < 1e-2)
-    assert np.array_equal(c[:4], exact[:4])
+    for n in range(4):
+        assert _cn_exact_ratio(o, n) == int(exact[n])
     flat = o.HG / float(o.MG[0])
     assert flat.min() > 0.9 and flat.max() < 1.1

@@ -25,9 +25,27 @@ class Problem:
     mode: str = "shared"     # "shared" (Algorithm 2), "independent" (Algorithm 1), "rosenbluth"
     stream: int = 0          # xored into the key's high word (problem id in a batch)
 
+    warmup: bool = True      # start with short epochs (see schedule())
+
     @property
     def total_tours(self) -> int:
-        return self.n_sequences * self.tours_per_epoch * self.epochs
+        return self.n_sequences * sum(self.schedule())
+
+    def schedule(self):
+        """Tours per sequence of each epoch (one merge after each).
+
+        With warm-up the first tours_per_epoch tours are split into epochs of
+        1, 1, 2, 4, ..., tours_per_epoch / 2 tours, so that the sequences start
+        sharing their running averages after their first tour; the remaining
+        epochs have tours_per_epoch tours.  The total is epochs * tours_per_epoch
+        either way."""
+        T = self.tours_per_epoch
+        if not self.warmup or T == 1 or (T & (T - 1)) != 0:
+            return [T] * self.epochs
+        head = [1]
+        while sum(head) < T:
+            head.append(sum(head))
+        return head + [T] * (self.epochs - 1)
 
     def as_dict(self):
         return asdict(self)
@@ -37,14 +55,16 @@ class Problem:
 
 
 # Plain flatPERM: one sequence, square lattice, n_max = 20, 10^5 tours, seed 1.
-PLAIN_2D = Problem(dim=2, n_max=20, n_sequences=1, tours_per_epoch=100_000, epochs=1, seed=1)
+PLAIN_2D = Problem(dim=2, n_max=20, n_sequences=1, tours_per_epoch=100_000, epochs=1, seed=1,
+                   warmup=False)
 
 # Parallel flatPERM on Z^2: 4096 sequences sharing W, a merge every 64 tours,
-# n_max = 500, 10^7 tours in total -> 38 epochs of 4096 * 64 tours (9,961,472).
+# n_max = 500, 10^7 tours in total -> 38 epochs' worth of 4096 * 64 tours
+# (9,961,472), the first 64 tours of each sequence in warm-up epochs.
 PARALLEL_2D = Problem(dim=2, n_max=500, n_sequences=4096, tours_per_epoch=64, epochs=38, seed=2)
 
 # Parallel flatPERM on Z^3: 16384 sequences, a merge every 32 tours, n_max = 1000,
-# 16 epochs (8,388,608 tours).
+# 16 epochs' worth (8,388,608 tours), the first 32 tours in warm-up epochs.
 PARALLEL_3D = Problem(dim=3, n_max=1000, n_sequences=16384, tours_per_epoch=32, epochs=16, seed=3)
 
 
