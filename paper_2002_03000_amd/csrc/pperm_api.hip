@@ -26,6 +26,7 @@ struct pperm_ctx {
     uint32_t team_lanes;      // TS: lanes per walk
     uint32_t slots_log2;
     uint32_t lds_team_bytes;
+    uint32_t lds_wg_bytes;
     uint32_t workgroups;
     uint64_t merged_tours;    // pooled tours merged so far (per sequence in independent mode)
     uint64_t open_tours;      // tours per sequence run since the last merge
@@ -69,7 +70,8 @@ uint32_t key_bytes(uint32_t dim) { return dim == 2 ? 4u : 8u; }
 struct Shape {
     uint32_t team_lanes;
     uint32_t slots;
-    uint32_t lds_team_bytes;
+    uint32_t lds_team_bytes;   // occupancy table + slot ids of one walk
+    uint32_t lds_wg_bytes;     // LDS of one workgroup
     uint32_t walks_per_wave;
 };
 
@@ -86,13 +88,15 @@ int resolve_shape(const pperm_config* c, Shape* sh) {
     uint32_t wpw = c->walks_per_wave;
     if (wpw == 0) {
         // default shape, narrowed until the walks of one workgroup fit in LDS
-        wpw = (c->dim == 2) ? 4u : 2u;
-        while (wpw > 1 && (uint64_t)sh->lds_team_bytes * wpw > kLdsLimit) wpw >>= 1;
+        wpw = 1u;
     }
     if (!is_pow2(wpw) || wpw > (c->dim == 2 ? 16u : 8u)) return PPERM_EINVAL;
     sh->walks_per_wave = wpw;
     sh->team_lanes = 64u / wpw;
-    if ((uint64_t)sh->lds_team_bytes * wpw > kLdsLimit) return PPERM_EINVAL;
+    // the wave-per-walk kernel also keeps the sequence's sums in LDS
+    sh->lds_wg_bytes = (wpw == 1) ? sh->lds_team_bytes + (uint32_t)align_up(c->n_max + 1u, 16) * 16u
+                                  : sh->lds_team_bytes * wpw;
+    if (sh->lds_wg_bytes > kLdsLimit) return PPERM_EINVAL;
     return PPERM_OK;
 }
 
@@ -209,15 +213,15 @@ int pperm_create(const pperm_config* cfg, void* d_workspace, size_t bytes, void*
     x->team_lanes = sh.team_lanes;
     x->slots_log2 = log2u(sh.slots);
     x->lds_team_bytes = sh.lds_team_bytes;
+    x->lds_wg_bytes = sh.lds_wg_bytes;
 
     hipError_t e = hipGetDevice(&x->device);
     if (e != hipSuccess) { delete x; return device_error(e, "hipGetDevice"); }
     int cus = 0;
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, x->device);
     if (e != hipSuccess) { delete x; return device_error(e, "hipDeviceGetAttribute"); }
-    const uint32_t lds_wg = sh.lds_team_bytes * sh.walks_per_wave;
     int per_cu = 0;
-    e = run_kernel_lds_ok(cfg->dim, sh.team_lanes, lds_wg, &per_cu);
+    e = run_kernel_lds_ok(cfg->dim, sh.team_lanes, sh.lds_wg_bytes, &per_cu);
     if (e != hipSuccess) { delete x; return device_error(e, "occupancy"); }
     if (per_cu < 1) { delete x; return PPERM_EINVAL; }
     uint64_t wgs = ((uint64_t)cfg->n_sequences + sh.walks_per_wave - 1) / sh.walks_per_wave;
@@ -274,9 +278,7 @@ int pperm_run_tours(pperm_ctx* x, uint32_t tours) {
     a.step_cap = (uint32_t)cap;
 
     HIP_TRY(launch_reset_ctrl(a.ctrl, x->stream));
-    const uint32_t wpw = 64u / x->team_lanes;
-    HIP_TRY(launch_run(a, x->cfg.dim, x->team_lanes, x->workgroups, x->lds_team_bytes * wpw,
-                       x->stream));
+    HIP_TRY(launch_run(a, x->cfg.dim, x->team_lanes, x->workgroups, x->lds_wg_bytes, x->stream));
     x->open_tours = per_seq_total;
     return PPERM_OK;
 }

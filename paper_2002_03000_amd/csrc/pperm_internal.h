@@ -30,14 +30,15 @@ struct __attribute__((aligned(16))) SumRec {
     uint32_t h;
 };
 
-// 32-byte pending-copy entry.
+// 32-byte pending-copy entry: the length and weight (m * 2^e) the copies
+// resume from, how many are still pending, and the packed endpoint site.
 struct __attribute__((aligned(16))) StackEntry {
     uint32_t n;
     uint32_t remaining;
     int32_t e;
     uint32_t pad0;
     double m;
-    uint64_t pad1;
+    uint64_t key;
 };
 
 struct RunArgs {
