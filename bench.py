@@ -36,6 +36,7 @@ WORKLOADS = {
     "parallel2d": workloads.PARALLEL_2D,
     "parallel3d": workloads.PARALLEL_3D,
     "plain2d": workloads.PLAIN_2D,
+    "batched": None,          # the 256-problem mix, see run_batched()
 }
 
 
@@ -76,6 +77,7 @@ def main():
     ap.add_argument("--epochs", type=int, default=0, help="override the epoch count (profiling)")
     ap.add_argument("--walks-per-wave", type=int, default=0)
     ap.add_argument("--hash-slots", type=int, default=0)
+    ap.add_argument("--problems", type=int, default=0, help="batched: use the first P problems of the mix")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
 
@@ -83,6 +85,10 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding "
               "of the method is described in the design notes, not run.", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batched":
+        run_batched(args)
+        return
 
     import numpy as np
     import torch
@@ -173,6 +179,159 @@ def main():
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(p)
     print(json.dumps(line), flush=True)
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def run_batched(args, plain_budget_s=40.0):
+    """The 256-problem mix as one batched job: in each round every problem that
+    still has an epoch runs it, all of them in one batched launch, then each
+    merges.  Beside it: the same problems on the single-problem path one at a
+    time (a time-bounded prefix of the mix), and the oracle on a sample."""
+    import numpy as np
+    import torch
+    from paper_2002_03000_amd import Batch, ParallelFlatPERM
+
+    mix = workloads.batched_mix()
+    if args.problems:
+        mix = mix[:args.problems]
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    scheds = [p.schedule() for p in mix]
+    rounds = max(len(s) for s in scheds)
+
+    def make(p, offset):
+        return ParallelFlatPERM(p.dim, p.n_max, p.n_sequences, p.seed + offset, mode=p.mode,
+                                stream_id=p.stream)
+
+    batch = Batch(len(mix))
+    # warm-up: the first two epochs of a few problems, their own seeds
+    warm = [make(p, 7_000_000) for p in mix[:8]]
+    for r in range(2):
+        batch.run_tours(warm, [s[r] for s in scheds[:8]])
+        for g in warm:
+            g.merge_epoch()
+    torch.cuda.synchronize()
+    for g in warm:
+        g.close()
+    del warm
+
+    steps_total, elapsed_total, events = 0, 0.0, []
+    results = []
+    for k in range(args.steps):
+        probs = [make(p, k) for p in mix]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        last = t0
+        for r in range(rounds):
+            tours = [s[r] if r < len(s) else 0 for s in scheds]
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            batch.run_tours(probs, tours)
+            b.record(stream)
+            events.append((a, b))
+            for g, t in zip(probs, tours):
+                if t:
+                    g.merge_epoch()
+            torch.cuda.synchronize()
+            if time.perf_counter() - last > 10:
+                last = time.perf_counter()
+                _log(f"batched job {k}: round {r + 1}/{rounds}, {last - t0:.1f} s")
+        ests = [g.estimates() for g in probs]
+        torch.cuda.synchronize()
+        elapsed_total += time.perf_counter() - t0
+        by_dim = {2: 0, 3: 0}
+        for p, g in zip(mix, probs):
+            by_dim[p.dim] += g.stats()["steps"]
+        steps_total += sum(by_dim.values())
+        results.append(ests)
+        for g in probs:
+            g.close()
+        del probs
+        _log(f"batched job {k} done: {elapsed_total:.1f} s so far")
+
+    run_ms = sum(a.elapsed_time(b) for a, b in events)
+    value = steps_total / elapsed_total
+    ops = (ALG_OPS_PER_STEP[2] * by_dim[2] + ALG_OPS_PER_STEP[3] * by_dim[3]) / max(1, sum(by_dim.values()))
+    achieved = steps_total / (run_ms / 1e3) * ops / 1e12
+
+    # plain path, one problem at a time, same problems and seeds (offset 0)
+    t0 = time.perf_counter()
+    plain_steps, plain_problems, plain_epochs = 0, 0, 0
+    for p, sch in zip(mix, scheds):
+        g = make(p, 0)
+        for T in sch:
+            g.run_tours(T)
+            g.merge_epoch()
+            torch.cuda.synchronize()
+            plain_epochs += 1
+            if time.perf_counter() - t0 > plain_budget_s:
+                break
+        g.estimates()
+        plain_steps += g.stats()["steps"]
+        g.close()
+        plain_problems += 1
+        if time.perf_counter() - t0 > plain_budget_s:
+            break
+    plain_dt = time.perf_counter() - t0
+    _log(f"plain path: {plain_problems} problems, {plain_epochs} epochs in {plain_dt:.1f} s")
+
+    total_tours = sum(p.total_tours for p in mix)
+    line = {
+        "metric": "walk-steps/s (parallel flatPERM, 1 GPU)",
+        "value": value,
+        "unit": "walk-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": 1,
+        "ms_per_step": elapsed_total * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (walks grown from parameters; seeds per problem)",
+        "config": {"workload": f"batched mix of {len(mix)} independent problems (seed 4): d in {{2,3}}, "
+                               f"n_max in [64,2048], N in 64..1024, {total_tours} tours in total, "
+                               f"{rounds} batched rounds",
+                   "problems": len(mix), "rounds": rounds,
+                   "walk_steps_per_job": steps_total // args.steps},
+        "plain_path": {"value": plain_steps / plain_dt, "unit": "walk-steps/s",
+                       "sample": f"the first {plain_problems} problems of the mix one at a time "
+                                 f"({plain_epochs} epochs, {plain_steps} walk-steps) in {plain_dt:.2f} s"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
+                     "frac": achieved / ALU_PEAK_TOPS, "traffic": None,
+                     "kernel": "batch_kernel", "avg_launch_ms": run_ms / len(events),
+                     "alg_ops_per_step": ops},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_mix(mix)
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline_mix(mix, budget_s=15.0):
+    """The oracle on the mix's problems one at a time, epoch by epoch, until the
+    time budget is spent."""
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
+    t0 = time.perf_counter()
+    steps, done = 0, 0
+    for p in mix:
+        o = oracle.Oracle(p.dim, p.n_max, p.n_sequences, p.seed, stream=p.stream, threads=threads)
+        for T in p.schedule():
+            o.run_tours(T)
+            o.merge_epoch()
+            done += 1
+            if time.perf_counter() - t0 > budget_s:
+                break
+        steps += o.walk_steps()
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": steps / dt, "unit": "walk-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"the mix's problems in order, {done} epochs ({steps} walk-steps) in {dt:.2f} s"}
 
 
 if __name__ == "__main__":

@@ -133,6 +133,23 @@ int pperm_run_tours(pperm_ctx* ctx, uint32_t tours_per_sequence);
  * Asynchronous. */
 int pperm_merge_epoch(pperm_ctx* ctx);
 
+/* Device bytes of the scratch a batched launch of `count` problems needs. */
+int pperm_batch_workspace_bytes(size_t count, size_t* bytes);
+
+/* Batched epoch step: every context ctxs[i] runs tours_each[i] more tours (0 =
+ * none), exactly as pperm_run_tours would, in persistent launches that share the
+ * GPU between all of them; each context's results are bit-identical to running
+ * it alone (a single problem is itself run as a batch of one).  Problems are
+ * grouped by the LDS their walks need; each group runs on its own stream, forked
+ * from and joined back into `hip_stream` (NULL: the default stream), which must
+ * be ordered after all earlier work of the contexts (simplest: create every
+ * context on `hip_stream`).  d_workspace: caller-owned device memory of at least
+ * pperm_batch_workspace_bytes(count), 256-byte aligned, not in use by another
+ * batch in flight.  Not thread-safe per device.  Errors: EINVAL (bad arguments,
+ * a context twice, contexts on another device), EOVERFLOW, EDEVICE. */
+int pperm_run_batch(pperm_ctx* const* ctxs, size_t count, const uint32_t* tours_each,
+                    void* d_workspace, size_t bytes, void* hip_stream);
+
 /* Synchronise the stream and read the merged state into caller-owned host
  * buffers of `len` >= n_max + 1 entries:
  *   log_cn[n] = log of the estimate of c_n (eqn (4); the mean of eqn (7) in

@@ -48,6 +48,8 @@ SIGNATURES = {
     "pperm_create": (_int, [_c.POINTER(Config), _vp, _sz, _vp, _c.POINTER(_vp)]),
     "pperm_run_tours": (_int, [_vp, _u32]),
     "pperm_merge_epoch": (_int, [_vp]),
+    "pperm_batch_workspace_bytes": (_int, [_sz, _c.POINTER(_sz)]),
+    "pperm_run_batch": (_int, [_c.POINTER(_vp), _sz, _c.POINTER(_u32), _vp, _sz, _vp]),
     "pperm_estimates": (_int, [_vp, _c.POINTER(_c.c_double), _c.POINTER(_u64), _c.POINTER(_u64), _sz]),
     "pperm_sequence_stats": (_int, [_vp, _c.POINTER(SeqStats), _sz]),
     "pperm_stats": (_int, [_vp, _c.POINTER(SeqStats)]),

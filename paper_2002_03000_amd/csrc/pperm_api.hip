@@ -8,6 +8,8 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -31,6 +33,8 @@ struct pperm_ctx {
     uint64_t merged_tours;    // pooled tours merged so far (per sequence in independent mode)
     uint64_t open_tours;      // tours per sequence run since the last merge
     int sticky_error;
+    ProblemDesc desc;         // host copy of the device-resident problem descriptor
+    ProblemDesc* desc_dev;
 };
 
 namespace {
@@ -50,8 +54,8 @@ int device_error(hipError_t e, const char* what) {
 
 constexpr uint32_t kMaxNmax = 32766;
 constexpr uint32_t kMaxSlots = 65536;
-constexpr uint32_t kMaxStackSlots = 65536;
-constexpr uint32_t kLdsLimit = 65536;    // bytes of LDS one workgroup may take
+constexpr uint32_t kLdsLimit = 163840;   // bytes of LDS one gfx950 workgroup may take
+constexpr uint32_t kTeamLdsLimit = 65536;
 constexpr uint32_t kDefaultCap = 1u << 31;
 
 uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
@@ -96,7 +100,7 @@ int resolve_shape(const pperm_config* c, Shape* sh) {
     // the wave-per-walk kernel also keeps the sequence's sums in LDS
     sh->lds_wg_bytes = (wpw == 1) ? sh->lds_team_bytes + (uint32_t)align_up(c->n_max + 1u, 16) * 16u
                                   : sh->lds_team_bytes * wpw;
-    if (sh->lds_wg_bytes > kLdsLimit) return PPERM_EINVAL;
+    if (sh->lds_wg_bytes > (wpw == 1 ? kLdsLimit : kTeamLdsLimit)) return PPERM_EINVAL;
     return PPERM_OK;
 }
 
@@ -119,8 +123,8 @@ void compute_layout(const pperm_config* c, pperm_layout* L) {
     const bool indep = (c->mode == PPERM_INDEPENDENT);
     Shape sh;
     resolve_shape(c, &sh);
-    const uint64_t stack_slots =
-        align_up(N < kMaxStackSlots ? N : kMaxStackSlots, sh.walks_per_wave);
+    // one copy stack per sequence (a sequence runs on one wavefront at a time)
+    const uint64_t stack_slots = align_up(N, sh.walks_per_wave);
     const uint64_t chunks = (N + 63) / 64;
     uint64_t off = 0;
     auto take = [&](uint64_t bytes) {
@@ -139,7 +143,7 @@ void compute_layout(const pperm_config* c, pperm_layout* L) {
     L->m = take(N * 4);
     L->t = take(N * 8);
     L->stats = take(N * STATS_WORDS * 8);
-    L->ctrl = take(CTRL_WORDS * 4);
+    L->ctrl = take(CTRL_WORDS * 4 + sizeof(ProblemDesc));
     // private scratch, not zeroed: copy stacks, merge partials (records + counts, x2)
     L->stack = take(stack_slots * c->n_max * sizeof(StackEntry));
     L->scratch = take(2 * chunks * row * (sizeof(SumRec) + 8));
@@ -231,11 +235,40 @@ int pperm_create(const pperm_config* cfg, void* d_workspace, size_t bytes, void*
     if (wgs > by_stack) wgs = by_stack;
     x->workgroups = (uint32_t)wgs;
 
+    int max_lds = 0;
+    e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, x->device);
+    if (e != hipSuccess) { delete x; return device_error(e, "hipDeviceGetAttribute"); }
+    if (sh.lds_wg_bytes > (uint32_t)max_lds) { delete x; return PPERM_EINVAL; }
+
+    // the device-resident description of this problem (read by the growth kernel)
+    ProblemDesc& d = x->desc;
+    memset(&d, 0, sizeof(d));
+    d.L = at<SumRec>(x, L.L);
+    d.G = at<SumRec>(x, L.G);
+    d.MG = at<uint64_t>(x, L.MG);
+    d.m = at<uint32_t>(x, L.m);
+    d.t = at<uint64_t>(x, L.t);
+    d.stats = at<uint64_t>(x, L.stats);
+    d.stack = at<StackEntry>(x, L.stack);
+    d.ctrl = at<uint32_t>(x, L.ctrl);
+    d.dim = cfg->dim;
+    d.N = cfg->n_sequences;
+    d.n_max = cfg->n_max;
+    d.row = L.row;
+    d.mode = cfg->mode;
+    d.slots_log2 = x->slots_log2;
+    d.lds_team_bytes = sh.lds_team_bytes;
+    d.key0 = (uint32_t)cfg->seed;
+    d.key1 = (uint32_t)(cfg->seed >> 32) ^ cfg->stream_id;
+    x->desc_dev = reinterpret_cast<ProblemDesc*>(at<uint32_t>(x, L.ctrl) + CTRL_WORDS);
+
     // zero the state (G .. ctrl are contiguous) and seed the digests
     const uint64_t zero_bytes = L.ctrl + CTRL_WORDS * 4 - L.G;
     e = launch_init_state(at<uint64_t>(x, L.stats), cfg->n_sequences, x->ws + L.G, zero_bytes,
                           x->stream);
     if (e != hipSuccess) { delete x; return device_error(e, "init_state"); }
+    e = hipMemcpyAsync(x->desc_dev, &x->desc, sizeof(ProblemDesc), hipMemcpyHostToDevice, x->stream);
+    if (e != hipSuccess) { delete x; return device_error(e, "descriptor copy"); }
     *out = x;
     return PPERM_OK;
 }
@@ -278,7 +311,22 @@ int pperm_run_tours(pperm_ctx* x, uint32_t tours) {
     a.step_cap = (uint32_t)cap;
 
     HIP_TRY(launch_reset_ctrl(a.ctrl, x->stream));
-    HIP_TRY(launch_run(a, x->cfg.dim, x->team_lanes, x->workgroups, x->lds_wg_bytes, x->stream));
+    if (x->team_lanes == 64) {
+        // one walk per wavefront: the problem alone is a batch of one
+        BatchArgs b;
+        memset(&b, 0, sizeof(b));
+        b.entries = nullptr;
+        b.single.desc = x->desc_dev;
+        b.single.tours = tours;
+        b.single.step_cap = a.step_cap;
+        b.single.first_item = 0;
+        b.count = 1;
+        b.total_items = N;
+        b.queue = a.ctrl + CTRL_QUEUE;
+        HIP_TRY(launch_batch(b, x->workgroups, x->lds_wg_bytes, x->stream));
+    } else {
+        HIP_TRY(launch_run(a, x->cfg.dim, x->team_lanes, x->workgroups, x->lds_wg_bytes, x->stream));
+    }
     x->open_tours = per_seq_total;
     return PPERM_OK;
 }
@@ -327,6 +375,165 @@ int pperm_merge_epoch(pperm_ctx* x) {
     }
     x->merged_tours += (uint64_t)N * x->open_tours;
     x->open_tours = 0;
+    return PPERM_OK;
+}
+
+// ---- batched launches --------------------------------------------------------
+namespace {
+
+constexpr int kBatchStreams = 4;
+
+struct DeviceStreams {
+    bool ready = false;
+    hipStream_t s[kBatchStreams];
+    hipEvent_t fork;
+    hipEvent_t join[kBatchStreams];
+};
+
+std::mutex g_batch_mutex;
+DeviceStreams g_streams[64];
+
+int batch_streams(int device, DeviceStreams** out) {
+    if (device < 0 || device >= 64) return PPERM_EINVAL;
+    DeviceStreams& d = g_streams[device];
+    if (!d.ready) {
+        for (int i = 0; i < kBatchStreams; ++i) {
+            HIP_TRY(hipStreamCreateWithFlags(&d.s[i], hipStreamNonBlocking));
+            HIP_TRY(hipEventCreateWithFlags(&d.join[i], hipEventDisableTiming));
+        }
+        HIP_TRY(hipEventCreateWithFlags(&d.fork, hipEventDisableTiming));
+        d.ready = true;
+    }
+    *out = &d;
+    return PPERM_OK;
+}
+
+struct BatchItem {
+    pperm_ctx* ctx;
+    uint32_t tours;
+    uint32_t lds;
+    double work;
+};
+
+}  // namespace
+
+int pperm_batch_workspace_bytes(size_t count, size_t* bytes) {
+    if (!bytes || count == 0) return PPERM_EINVAL;
+    *bytes = (size_t)align_up(count * sizeof(LaunchEntry), 256) + 256;
+    return PPERM_OK;
+}
+
+int pperm_run_batch(pperm_ctx* const* ctxs, size_t count, const uint32_t* tours_each,
+                    void* d_workspace, size_t bytes, void* hip_stream) {
+    if (!ctxs || !tours_each || !d_workspace || count == 0) return PPERM_EINVAL;
+    size_t need = 0;
+    pperm_batch_workspace_bytes(count, &need);
+    if (bytes < need || ((uintptr_t)d_workspace & 255u)) return PPERM_EINVAL;
+    hipStream_t stream = (hipStream_t)hip_stream;
+    int device = -1;
+    HIP_TRY(hipGetDevice(&device));
+
+    // validate and size every problem's share
+    std::vector<BatchItem> items;
+    items.reserve(count);
+    for (size_t i = 0; i < count; ++i) {
+        pperm_ctx* x = ctxs[i];
+        if (!x || x->device != device) return PPERM_EINVAL;
+        for (size_t j = 0; j < i; ++j)
+            if (ctxs[j] == x) return PPERM_EINVAL;          // a problem at most once per batch
+        if (tours_each[i] == 0) continue;
+        const uint64_t N = x->cfg.n_sequences;
+        const uint64_t per_seq_total = x->open_tours + tours_each[i];
+        const uint64_t pooled = (x->cfg.mode == PPERM_SHARED) ? x->merged_tours + N * per_seq_total
+                                                              : x->merged_tours + per_seq_total;
+        if (pooled > 0xFFFFFFFFull || per_seq_total > 0xFFFFFFFFull) return PPERM_EOVERFLOW;
+        const uint32_t lds = x->desc.lds_team_bytes + x->desc.row * (uint32_t)sizeof(SumRec);
+        items.push_back({x, tours_each[i], lds,
+                         (double)N * tours_each[i] * (double)(x->cfg.n_max + 1)});
+    }
+    if (items.empty()) return PPERM_OK;
+
+    // LDS size classes (a launch gives every wave the largest share of its class);
+    // inside a class the largest expected work goes first
+    std::sort(items.begin(), items.end(), [](const BatchItem& a, const BatchItem& b) {
+        if (a.lds != b.lds) return a.lds < b.lds;
+        return a.work > b.work;
+    });
+    struct Class { size_t begin, end; uint32_t lds; uint32_t total; };
+    std::vector<Class> classes;
+    for (size_t i = 0; i < items.size();) {
+        uint32_t cls = 8192;
+        while (cls < items[i].lds) cls <<= 1;
+        size_t j = i;
+        while (j < items.size() && items[j].lds <= cls) ++j;
+        classes.push_back({i, j, 0, 0});
+        i = j;
+    }
+    if (classes.size() > (size_t)kBatchStreams) {
+        // fold the smallest classes together (their waves then take the larger share)
+        while (classes.size() > (size_t)kBatchStreams) {
+            classes[1].begin = classes[0].begin;
+            classes.erase(classes.begin());
+        }
+    }
+    std::vector<LaunchEntry> host(items.size());
+    for (Class& c : classes) {
+        uint32_t first = 0, lds = 0;
+        // the class's entries in LPT order (largest expected work first)
+        std::sort(items.begin() + c.begin, items.begin() + c.end,
+                  [](const BatchItem& a, const BatchItem& b) { return a.work > b.work; });
+        for (size_t i = c.begin; i < c.end; ++i) {
+            host[i].desc = items[i].ctx->desc_dev;
+            host[i].tours = items[i].tours;
+            uint64_t cap = items[i].ctx->cfg.step_cap;
+            if (cap == 0) {
+                cap = 4096ull * items[i].tours * (items[i].ctx->cfg.n_max + 1ull);
+                if (cap > kDefaultCap) cap = kDefaultCap;
+            }
+            host[i].step_cap = (uint32_t)cap;
+            host[i].first_item = first;
+            host[i].pad = 0;
+            first += items[i].ctx->cfg.n_sequences;
+            lds = std::max(lds, items[i].lds);
+        }
+        c.lds = lds;
+        c.total = first;
+    }
+
+    std::lock_guard<std::mutex> lock(g_batch_mutex);
+    DeviceStreams* ds = nullptr;
+    int rc = batch_streams(device, &ds);
+    if (rc) return rc;
+    unsigned char* ws = (unsigned char*)d_workspace;
+    LaunchEntry* dev_entries = reinterpret_cast<LaunchEntry*>(ws);
+    uint32_t* queues = reinterpret_cast<uint32_t*>(ws + align_up(count * sizeof(LaunchEntry), 256));
+    HIP_TRY(hipMemcpyAsync(dev_entries, host.data(), host.size() * sizeof(LaunchEntry),
+                           hipMemcpyHostToDevice, stream));
+    HIP_TRY(launch_reset_ctrl(queues, stream));   // classes use queue words 0..3
+    for (size_t c = 1; c < classes.size(); ++c) HIP_TRY(launch_reset_ctrl(queues + 4 * c, stream));
+    HIP_TRY(hipEventRecord(ds->fork, stream));
+    int cus = 0;
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
+    for (size_t c = 0; c < classes.size(); ++c) {
+        const Class& C = classes[c];
+        int per_cu = 0;
+        HIP_TRY(batch_occupancy(C.lds, &per_cu));
+        if (per_cu < 1) return PPERM_EINVAL;
+        uint64_t wgs = (uint64_t)per_cu * cus;
+        if (wgs > C.total) wgs = C.total;
+        BatchArgs b;
+        memset(&b, 0, sizeof(b));
+        b.entries = dev_entries + C.begin;
+        b.single = host[C.begin];
+        b.count = (uint32_t)(C.end - C.begin);
+        b.total_items = C.total;
+        b.queue = queues + 4 * c;
+        HIP_TRY(hipStreamWaitEvent(ds->s[c], ds->fork, 0));
+        HIP_TRY(launch_batch(b, (uint32_t)wgs, C.lds, ds->s[c]));
+        HIP_TRY(hipEventRecord(ds->join[c], ds->s[c]));
+    }
+    for (size_t c = 0; c < classes.size(); ++c) HIP_TRY(hipStreamWaitEvent(stream, ds->join[c], 0));
+    for (const BatchItem& it : items) it.ctx->open_tours += it.tours;
     return PPERM_OK;
 }
 

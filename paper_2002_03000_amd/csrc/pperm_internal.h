@@ -61,6 +61,46 @@ struct RunArgs {
     uint32_t step_cap;
 };
 
+// Everything the growth kernel needs to know about one problem; written once
+// into the problem's workspace when its context is created.
+struct ProblemDesc {
+    SumRec* L;            // [N][row]
+    const SumRec* G;      // shared: [row]; independent: [N][row]
+    const uint64_t* MG;   // shared: [1];   independent: [N]
+    uint32_t* m;          // [N]
+    uint64_t* t;          // [N]
+    uint64_t* stats;      // [N][STATS_WORDS]
+    StackEntry* stack;    // [N][n_max]
+    uint32_t* ctrl;       // CTRL_WORDS
+    uint32_t dim;
+    uint32_t N;
+    uint32_t n_max;
+    uint32_t row;
+    uint32_t mode;
+    uint32_t slots_log2;
+    uint32_t lds_team_bytes;   // occupancy table + slot ids; the sums row follows
+    uint32_t key0, key1;
+    uint32_t pad;
+};
+
+// One problem's share of a launch: its tours, its step cap, and the index of
+// its first (problem, sequence) item in the launch's queue.
+struct LaunchEntry {
+    const ProblemDesc* desc;
+    uint32_t tours;
+    uint32_t step_cap;
+    uint32_t first_item;
+    uint32_t pad;
+};
+
+struct BatchArgs {
+    const LaunchEntry* entries;   // count > 1: sorted by first_item
+    LaunchEntry single;           // count == 1
+    uint32_t count;
+    uint32_t total_items;
+    uint32_t* queue;              // zeroed before the launch
+};
+
 struct MergeArgs {
     const SumRec* in;      // [rows][row]
     SumRec* out;           // [ceil(rows/64)][row], or G when final
@@ -82,6 +122,8 @@ hipError_t launch_run(const RunArgs& a, uint32_t dim, uint32_t team_lanes, uint3
 hipError_t run_kernel_lds_ok(uint32_t dim, uint32_t team_lanes, uint32_t lds_bytes,
                              int* blocks_per_cu);
 hipError_t launch_merge_pass(const MergeArgs& a, hipStream_t s);
+hipError_t launch_batch(const BatchArgs& b, uint32_t workgroups, uint32_t lds_bytes, hipStream_t s);
+hipError_t batch_occupancy(uint32_t lds_bytes, int* blocks_per_cu);
 hipError_t launch_merge_counts(const uint32_t* m, uint32_t N, uint64_t* MG, uint32_t* zero_m,
                                hipStream_t s);
 hipError_t launch_merge_independent(SumRec* L, uint32_t* m, SumRec* G, uint64_t* HG, uint64_t* MG,

@@ -542,9 +542,12 @@ __device__ __forceinline__ uint64_t ufirst64(uint64_t v) {
 }
 __device__ __forceinline__ bool ubool(bool b) { return ufirst(b ? 1u : 0u) != 0u; }
 
+// One sequence's `tours` tours against frozen pooled sums (the whole hot path
+// of one walk); run by one wavefront.  Every value below is wave-uniform
+// except where a lane index enters (scan windows, Philox counters, deletions).
 template <int D>
-__global__ void __launch_bounds__(64)
-walker_kernel(RunArgs A, const SumRec* __restrict__ Gbase, SumRec* __restrict__ Lbase) {
+__device__ __forceinline__ void walk_sequence(const ProblemDesc& P, uint32_t tours, uint32_t cap,
+                                              uint32_t s, unsigned char* lds) {
     using L_ = Lat<D>;
     using Key = typename L_::Key;
     constexpr int NDIR = 2 * D;
@@ -554,14 +557,13 @@ walker_kernel(RunArgs A, const SumRec* __restrict__ Gbase, SumRec* __restrict__ 
     // LDS: the occupancy table, the slot id of every site of the walk, and the
     // sequence's own per-length sums (moved in at the start of the sequence's
     // tours and back out at their end)
-    extern __shared__ __align__(16) unsigned char lds[];
     Key* table = reinterpret_cast<Key*>(lds);
-    uint16_t* sid = reinterpret_cast<uint16_t*>(lds + (sizeof(Key) << A.slots_log2));
-    SumRec* Ls = reinterpret_cast<SumRec*>(lds + A.lds_team_bytes);
+    uint16_t* sid = reinterpret_cast<uint16_t*>(lds + (sizeof(Key) << P.slots_log2));
+    SumRec* Ls = reinterpret_cast<SumRec*>(lds + P.lds_team_bytes);
     const int lane = (int)threadIdx.x;
-    const uint32_t S = 1u << A.slots_log2;
+    const uint32_t S = 1u << P.slots_log2;
     const uint32_t smask = S - 1u;
-    const uint32_t hshift = 32u - A.slots_log2;
+    const uint32_t hshift = 32u - P.slots_log2;
 
     // probe-lane role: direction-major, W lanes per direction
     const int pdir = lane / W;
@@ -569,14 +571,16 @@ walker_kernel(RunArgs A, const SumRec* __restrict__ Gbase, SumRec* __restrict__ 
     const bool pvalid = pdir < NDIR;
     const int pdx = dir_dx(pdir), pdy = dir_dy(pdir), pdz = dir_dz(pdir);
 
-    const uint32_t n_max = A.n_max;
-    const uint32_t row = A.row;
-    const bool shared_mode = (A.mode == MODE_SHARED);
-    const bool control_mode = (A.mode != MODE_ROSENBLUTH);
-    const double pool = shared_mode ? (double)A.N : 1.0;
-    const uint64_t pool_u = shared_mode ? (uint64_t)A.N : 1ull;
-    const uint32_t cap = A.step_cap;
+    const uint32_t n_max = P.n_max;
+    const uint32_t row = P.row;
+    const bool shared_mode = (P.mode == MODE_SHARED);
+    const bool control_mode = (P.mode != MODE_ROSENBLUTH);
+    const double pool = shared_mode ? (double)P.N : 1.0;
+    const uint64_t pool_u = shared_mode ? (uint64_t)P.N : 1ull;
+    const SumRec* __restrict__ Gbase = P.G;
+    SumRec* __restrict__ Lbase = P.L;
 
+    // the empty table with the origin in it, slot id of site 0
     for (uint32_t i = (uint32_t)lane; i < S; i += 64) table[i] = (Key)0;
     wave_fence();
     const Key origin_key = L_::pack(0, 0, 0);
@@ -587,261 +591,285 @@ walker_kernel(RunArgs A, const SumRec* __restrict__ Gbase, SumRec* __restrict__ 
     }
     wave_fence();
 
-    StackEntry* stk = A.stack + (size_t)blockIdx.x * n_max;
-    uint64_t MGs = shared_mode ? A.MG[0] : 0ull;
+    // the copy stack of sequence s
+    StackEntry* stk = P.stack + (size_t)s * n_max;
+    uint64_t MGs = shared_mode ? P.MG[0] : 0ull;
 
-    for (;;) {
-        uint32_t got = 0u;
-        if (lane == 0) got = atomicAdd(&A.ctrl[CTRL_QUEUE], 1u);
-        const uint32_t s = ufirst(__shfl(got, 0, 64));
-        if (s >= A.N) break;
+    const size_t rb0 = (size_t)s * row;
+    SumRec* __restrict__ Lrow = Lbase + rb0;
+    const SumRec* __restrict__ Grow = shared_mode ? Gbase : Gbase + rb0;
+    if (!shared_mode) MGs = ufirst64(P.MG[s]);
+    const uint64_t t0 = ufirst64(P.t[s]);
+    uint32_t tlo = (uint32_t)t0;               // tour index: its low word keys the random numbers
+    uint32_t m = ufirst(P.m[s]);
+    for (uint32_t i = (uint32_t)lane; i <= n_max; i += 64u) Ls[i] = Lrow[i];
+    wave_fence();
+    SumRec rec0 = Ls[0];
+    // counters of this call, added to the sequence's totals at its end: the
+    // step count (scalar, it drives the cap) and one counter per lane of `cv`
+    // (lane i accumulates statistics word i)
+    uint32_t c_steps = 0, c_tours = 0, c_maxd = 0;
+    uint64_t cv = 0;
+    uint64_t digest = ufirst64(P.stats[(size_t)s * STATS_WORDS + ST_DIGEST]);
+    bool abort = false;
 
-        const size_t rb0 = (size_t)s * row;
-        SumRec* __restrict__ Lrow = Lbase + rb0;
-        const SumRec* __restrict__ Grow = shared_mode ? Gbase : Gbase + rb0;
-        if (!shared_mode) MGs = ufirst64(A.MG[s]);
-        const uint64_t t0 = ufirst64(A.t[s]);
-        uint32_t tlo = (uint32_t)t0;               // tour index: its low word keys the random numbers
-        uint32_t m = ufirst(A.m[s]);
-        for (uint32_t i = (uint32_t)lane; i <= n_max; i += 64u) Ls[i] = Lrow[i];
-        wave_fence();
-        SumRec rec0 = Ls[0];
-        // counters of this call, added to the sequence's totals at its end: the
-        // step count (scalar, it drives the cap) and one counter per lane of `cv`
-        // (lane i accumulates statistics word i)
-        uint32_t c_steps = 0, c_tours = 0, c_maxd = 0;
-        uint64_t cv = 0;
-        uint64_t digest = ufirst64(A.stats[(size_t)s * STATS_WORDS + ST_DIGEST]);
-        bool abort = false;
+    for (uint32_t tour = 0; tour < tours && !abort; ++tour) {
+        // ---- a pass through the empty walk (eqn (4), M) ----
+        const uint32_t tt = tlo;
+        tlo += 1u;
+        m += 1;
+        c_tours += 1;
+        XF w = {0.5, 1};                       // W_0 = 1
+        {
+            const XF r0 = xf_add(xf_of(rec0), w);
+            rec0.m = r0.m;
+            rec0.e = r0.e;
+            rec0.h += 1u;
+        }
+        // events of this tour; fewer than 2^32 because the step cap is at most
+        // 2^31 and every event either grows the walk or prunes a grown copy
+        uint32_t k = 0, kb = 0;
+        bool stale = true;
+        uint4 rb = make_uint4(0, 0, 0, 0);
+        uint32_t n = 0;
+        int ex = 0, ey = 0, ez = 0;
+        bool control = false;
+        uint32_t sp = 0, top_n = 0, top_rem = 0;
+        XF top_w = {0.0, 0};
+        uint64_t top_key = 0;
+        XF Lc = {0.0, 0};
+        // tours seen by the running average of eqn (6) (reading of Algorithm 2)
+        const double seen = (double)(MGs + pool_u * (uint64_t)m);
 
-        for (uint32_t tour = 0; tour < A.tours && !abort; ++tour) {
-            // ---- a pass through the empty walk (eqn (4), M) ----
-            const uint32_t tt = tlo;
-            tlo += 1u;
-            m += 1;
-            c_tours += 1;
-            XF w = {0.5, 1};                       // W_0 = 1
-            {
-                const XF r0 = xf_add(xf_of(rec0), w);
-                rec0.m = r0.m;
-                rec0.e = r0.e;
-                rec0.h += 1u;
+        for (;;) {
+            bool bt = false;
+            // ---- the random block this step's event would draw (64 per pass) ----
+            if (stale || (k - kb) >= 64u) {
+                kb = k;
+                stale = false;
+                rb = philox10(make_uint4(kb + (uint32_t)lane, 0u, tt, s), P.key0, P.key1);
             }
-            // events of this tour; fewer than 2^32 because the step cap is at most
-            // 2^31 and every event either grows the walk or prunes a grown copy
-            uint32_t k = 0, kb = 0;
-            bool stale = true;
-            uint4 rb = make_uint4(0, 0, 0, 0);
-            uint32_t n = 0;
-            int ex = 0, ey = 0, ez = 0;
-            bool control = false;
-            uint32_t sp = 0, top_n = 0, top_rem = 0;
-            XF top_w = {0.0, 0};
-            uint64_t top_key = 0;
-            XF Lc = {0.0, 0};
-            // tours seen by the running average of eqn (6) (reading of Algorithm 2)
-            const double seen = (double)(MGs + pool_u * (uint64_t)m);
+            const uint32_t li = k - kb;
+            const uint32_t B0 = __builtin_amdgcn_readlane(rb.x, li);
+            const uint32_t B1 = __builtin_amdgcn_readlane(rb.y, li);
+            const uint32_t B2 = __builtin_amdgcn_readlane(rb.z, li);
 
+            // ---- one straight-line block: loads, first scan window, decision
+            // arithmetic (independent of the scan, so it fills the LDS latency) ----
+            // pooled sum of this length (read-only: scalar load) and this
+            // sequence's record of the next length
+            const XF Gc = xf_of(Grow[n]);
+            const SumRec nxt = Ls[n + 1];
+            // occupancy scan of the endpoint's 2d neighbours.  In a linear-probing
+            // run the key, if present, lies before the first empty slot, so a
+            // direction is occupied iff a window shows the key and free iff it
+            // shows an empty slot and no key.
+            const Key nk = L_::pack(ex + pdx, ey + pdy, ez + pdz);
+            const uint32_t home = L_::hash(nk) >> hshift;
+            uint32_t slot = (home + (uint32_t)poff) & smask;
+            Key v = table[slot];
+            // eqn (6): r = W / [W_n], [W_n] = sum / seen (own epoch data weighted
+            // N in Algorithm 2), evaluated as (W * seen) / sum; only used when a
+            // decision is due at this length
+            const XF sum = xf_add(Gc, xf_mul(Lc, pool));
+            const double r = xf_ratio(xf_mul(w, seen), sum);
+            const double u = ((double)(B1 >> 5) * 67108864.0 + (double)(B2 >> 6)) *
+                             (1.0 / 9007199254740992.0);
+            const double f = floor(r);
+            const uint32_t ub = ufirst((r >= 1.0 ? 1u : 0u) |
+                                       ((r != f && u < (f + 1.0) - r) ? 2u : 0u) |
+                                       (r == f ? 4u : 0u) | (u < r ? 8u : 0u));
+            // (r is only meaningful when a decision is due; keep the conversion defined)
+            const uint32_t fi = ufirst((uint32_t)((f >= 0.0 && f < 4294967295.0) ? f : 0.0));
+
+            uint32_t pending = (1u << NDIR) - 1u;
+            uint32_t freem = 0u;
+            uint32_t myslot = 0u;                 // slot this lane read when its direction resolved
+            bool myemp = false;                   // ... and whether it was empty
+            uint32_t base = (uint32_t)poff;
             for (;;) {
-                bool bt = false;
-                // ---- the random block this step's event would draw (64 per pass) ----
-                if (stale || (k - kb) >= 64u) {
-                    kb = k;
-                    stale = false;
-                    rb = philox10(make_uint4(kb + (uint32_t)lane, 0u, tt, s), A.key0, A.key1);
+                const bool act = pvalid && ((pending >> pdir) & 1u);
+                const bool emp = act && v == (Key)0;
+                if (act) {
+                    myslot = slot;
+                    myemp = emp;
                 }
-                const uint32_t li = k - kb;
-                const uint32_t B0 = __builtin_amdgcn_readlane(rb.x, li);
-                const uint32_t B1 = __builtin_amdgcn_readlane(rb.y, li);
-                const uint32_t B2 = __builtin_amdgcn_readlane(rb.z, li);
-
-                // ---- one straight-line block: loads, first scan window, decision
-                // arithmetic (independent of the scan, so it fills the LDS latency) ----
-                // pooled sum of this length (read-only: scalar load) and this
-                // sequence's record of the next length
-                const XF Gc = xf_of(Grow[n]);
-                const SumRec nxt = Ls[n + 1];
-                // occupancy scan of the endpoint's 2d neighbours.  In a linear-probing
-                // run the key, if present, lies before the first empty slot, so a
-                // direction is occupied iff a window shows the key and free iff it
-                // shows an empty slot and no key.
-                const Key nk = L_::pack(ex + pdx, ey + pdy, ez + pdz);
-                const uint32_t home = L_::hash(nk) >> hshift;
-                uint32_t slot = (home + (uint32_t)poff) & smask;
-                Key v = table[slot];
-                // eqn (6): r = W / [W_n], [W_n] = sum / seen (own epoch data weighted
-                // N in Algorithm 2), evaluated as (W * seen) / sum; only used when a
-                // decision is due at this length
-                const XF sum = xf_add(Gc, xf_mul(Lc, pool));
-                const double r = xf_ratio(xf_mul(w, seen), sum);
-                const double u = ((double)(B1 >> 5) * 67108864.0 + (double)(B2 >> 6)) *
-                                 (1.0 / 9007199254740992.0);
-                const double f = floor(r);
-                const uint32_t ub = ufirst((r >= 1.0 ? 1u : 0u) |
-                                           ((r != f && u < (f + 1.0) - r) ? 2u : 0u) |
-                                           (r == f ? 4u : 0u) | (u < r ? 8u : 0u));
-                // (r is only meaningful when a decision is due; keep the conversion defined)
-                const uint32_t fi = ufirst((uint32_t)((f >= 0.0 && f < 4294967295.0) ? f : 0.0));
-
-                uint32_t pending = (1u << NDIR) - 1u;
-                uint32_t freem = 0u;
-                uint32_t myslot = 0u;                 // slot this lane read when its direction resolved
-                bool myemp = false;                   // ... and whether it was empty
-                uint32_t base = (uint32_t)poff;
-                for (;;) {
-                    const bool act = pvalid && ((pending >> pdir) & 1u);
-                    const bool emp = act && v == (Key)0;
-                    if (act) {
-                        myslot = slot;
-                        myemp = emp;
-                    }
-                    // per direction: does its window show the key (2) / an empty slot (1)?
-                    const uint32_t code = group_or<W>((act && v == nk) ? 2u : (emp ? 1u : 0u));
-                    const uint64_t gh = __ballot(poff == 0 && (code & 2u));
-                    const uint64_t ge = __ballot(poff == 0 && (code & 1u));
-                    uint32_t hit_dirs = 0u, emp_dirs = 0u;
+                // per direction: does its window show the key (2) / an empty slot (1)?
+                const uint32_t code = group_or<W>((act && v == nk) ? 2u : (emp ? 1u : 0u));
+                const uint64_t gh = __ballot(poff == 0 && (code & 2u));
+                const uint64_t ge = __ballot(poff == 0 && (code & 1u));
+                uint32_t hit_dirs = 0u, emp_dirs = 0u;
 #pragma unroll
-                    for (int d = 0; d < NDIR; ++d) {
-                        hit_dirs |= (uint32_t)((gh >> (d * W - d)) & (1ull << d));
-                        emp_dirs |= (uint32_t)((ge >> (d * W - d)) & (1ull << d));
-                    }
-                    freem |= emp_dirs & ~hit_dirs & pending;
-                    pending &= ~(hit_dirs | emp_dirs);
-                    if (pending == 0u) break;
-                    // a run longer than the window: read the next W positions
-                    base += W;
-                    slot = (home + base) & smask;
-                    v = table[slot];
+                for (int d = 0; d < NDIR; ++d) {
+                    hit_dirs |= (uint32_t)((gh >> (d * W - d)) & (1ull << d));
+                    emp_dirs |= (uint32_t)((ge >> (d * W - d)) & (1ull << d));
                 }
-                const uint32_t a = (uint32_t)__popc(freem);
-                if (a == 0u) {
-                    cv += (lane == ST_TRAPS) ? 1ull : 0ull;
+                freem |= emp_dirs & ~hit_dirs & pending;
+                pending &= ~(hit_dirs | emp_dirs);
+                if (pending == 0u) break;
+                // a run longer than the window: read the next W positions
+                base += W;
+                slot = (home + base) & smask;
+                v = table[slot];
+            }
+            const uint32_t a = (uint32_t)__popc(freem);
+            if (a == 0u) {
+                cv += (lane == ST_TRAPS) ? 1ull : 0ull;
+                bt = true;
+            } else {
+                k += 1;
+                cv += (lane == ST_EVENTS) ? 1ull : 0ull;
+                bool pruned = false;
+                if (control) {
+                    if (ub & 1u) {
+                        // r >= 1: c = floor(r) with probability ceil(r) - r, else ceil(r)
+                        const uint32_t ci = (ub & 6u) ? fi : fi + 1u;
+                        if (ci > 1u) {
+                            w = xf_div(w, (double)ci);
+                            if (sp > 0u) {
+                                StackEntry e;
+                                e.n = top_n;
+                                e.remaining = top_rem;
+                                e.e = top_w.e;
+                                e.pad0 = 0u;
+                                e.m = top_w.m;
+                                e.key = top_key;
+                                stk[sp - 1] = e;
+                            }
+                            top_n = n;
+                            top_rem = ci - 1u;
+                            top_w = w;
+                            top_key = (uint64_t)L_::pack(ex, ey, ez);
+                            sp += 1;
+                            c_maxd = (sp > c_maxd) ? sp : c_maxd;
+                            cv += (lane == ST_ENRICH) ? 1ull
+                                  : ((lane == ST_COPIES) ? (uint64_t)(ci - 1u) : 0ull);
+                        }
+                    } else if (ub & 8u) {
+                        w = xf_div(sum, seen);     // r < 1, survives: W / r
+                    } else {
+                        pruned = true;             // r < 1, pruned with probability 1 - r
+                    }
+                }
+                if (pruned) {
+                    cv += (lane == ST_PRUNES) ? 1ull : 0ull;
                     bt = true;
                 } else {
-                    k += 1;
-                    cv += (lane == ST_EVENTS) ? 1ull : 0ull;
-                    bool pruned = false;
-                    if (control) {
-                        if (ub & 1u) {
-                            // r >= 1: c = floor(r) with probability ceil(r) - r, else ceil(r)
-                            const uint32_t ci = (ub & 6u) ? fi : fi + 1u;
-                            if (ci > 1u) {
-                                w = xf_div(w, (double)ci);
-                                if (sp > 0u) {
-                                    StackEntry e;
-                                    e.n = top_n;
-                                    e.remaining = top_rem;
-                                    e.e = top_w.e;
-                                    e.pad0 = 0u;
-                                    e.m = top_w.m;
-                                    e.key = top_key;
-                                    stk[sp - 1] = e;
-                                }
-                                top_n = n;
-                                top_rem = ci - 1u;
-                                top_w = w;
-                                top_key = (uint64_t)L_::pack(ex, ey, ez);
-                                sp += 1;
-                                c_maxd = (sp > c_maxd) ? sp : c_maxd;
-                                cv += (lane == ST_ENRICH) ? 1ull
-                                      : ((lane == ST_COPIES) ? (uint64_t)(ci - 1u) : 0ull);
-                            }
-                        } else if (ub & 8u) {
-                            w = xf_div(sum, seen);     // r < 1, survives: W / r
-                        } else {
-                            pruned = true;             // r < 1, pruned with probability 1 - r
-                        }
+                    // ---- Rosenbluth growth: the j-th free neighbour ----
+                    const uint32_t j = __umulhi(B0, a);
+                    uint32_t mm = freem;
+                    for (uint32_t i = 0; i < j; ++i) mm &= mm - 1u;
+                    const int dir = __ffs(mm) - 1;
+                    digest = (digest ^ (uint64_t)((uint32_t)dir | (a << 3))) * FNV_PRIME;
+                    // insertion slot: the first empty slot of the chosen direction's run
+                    const uint64_t bemp = __ballot(myemp);
+                    const uint32_t il =
+                        (uint32_t)__builtin_ctzll((bemp >> (dir * W)) & FIELD) + (uint32_t)(dir * W);
+                    const uint32_t ins_slot = __builtin_amdgcn_readlane(myslot, il);
+                    ex += dir_dx(dir);
+                    ey += dir_dy(dir);
+                    ez += dir_dz(dir);
+                    if (lane == 0) {
+                        table[ins_slot] = L_::pack(ex, ey, ez);
+                        sid[n + 1] = (uint16_t)ins_slot;
                     }
-                    if (pruned) {
-                        cv += (lane == ST_PRUNES) ? 1ull : 0ull;
-                        bt = true;
-                    } else {
-                        // ---- Rosenbluth growth: the j-th free neighbour ----
-                        const uint32_t j = __umulhi(B0, a);
-                        uint32_t mm = freem;
-                        for (uint32_t i = 0; i < j; ++i) mm &= mm - 1u;
-                        const int dir = __ffs(mm) - 1;
-                        digest = (digest ^ (uint64_t)((uint32_t)dir | (a << 3))) * FNV_PRIME;
-                        // insertion slot: the first empty slot of the chosen direction's run
-                        const uint64_t bemp = __ballot(myemp);
-                        const uint32_t il =
-                            (uint32_t)__builtin_ctzll((bemp >> (dir * W)) & FIELD) + (uint32_t)(dir * W);
-                        const uint32_t ins_slot = __builtin_amdgcn_readlane(myslot, il);
-                        ex += dir_dx(dir);
-                        ey += dir_dy(dir);
-                        ez += dir_dz(dir);
-                        if (lane == 0) {
-                            table[ins_slot] = L_::pack(ex, ey, ez);
-                            sid[n + 1] = (uint16_t)ins_slot;
-                        }
-                        w = xf_mul(w, (double)a);      // W *= a_+, eqn (2)
-                        if (ubool(w.e > EXP_LIMIT || w.e < -EXP_LIMIT)) {
-                            if (lane == 0) atomicOr(&A.ctrl[CTRL_ERR], ERR_RANGE);
-                        }
-                        n += 1;
-                        c_steps += 1;
-                        // ---- arrival: record into the running sums, eqn (4) ----
-                        const XF Lnew = xf_add(xf_of(nxt), w);
-                        SumRec nr;
-                        nr.m = Lnew.m;
-                        nr.e = Lnew.e;
-                        nr.h = nxt.h + 1u;
-                        if (lane == 0) Ls[n] = nr;
-                        Lc = Lnew;
-                        if (cap != 0u && c_steps >= cap) {
-                            abort = true;
-                            break;
-                        }
-                        if (n == n_max) bt = true;
-                        else control = control_mode;
+                    w = xf_mul(w, (double)a);      // W *= a_+, eqn (2)
+                    if (ubool(w.e > EXP_LIMIT || w.e < -EXP_LIMIT)) {
+                        if (lane == 0) atomicOr(&P.ctrl[CTRL_ERR], ERR_RANGE);
                     }
-                }
-                if (bt) {
-                    // ---- resume the most recent pending copy, or end the tour ----
-                    if (sp == 0u) break;
-                    const uint32_t rn = top_n;
-                    w = top_w;
-                    const uint64_t ekey = top_key;
-                    top_rem -= 1u;
-                    if (top_rem == 0u) {
-                        sp -= 1u;
-                        if (sp > 0u) {
-                            const StackEntry e = stk[sp - 1];
-                            top_n = ufirst(e.n);
-                            top_rem = ufirst(e.remaining);
-                            top_w = XF{e.m, e.e};
-                            top_key = ufirst64(e.key);
-                        }
+                    n += 1;
+                    c_steps += 1;
+                    // ---- arrival: record into the running sums, eqn (4) ----
+                    const XF Lnew = xf_add(xf_of(nxt), w);
+                    SumRec nr;
+                    nr.m = Lnew.m;
+                    nr.e = Lnew.e;
+                    nr.h = nxt.h + 1u;
+                    if (lane == 0) Ls[n] = nr;
+                    Lc = Lnew;
+                    if (cap != 0u && c_steps >= cap) {
+                        abort = true;
+                        break;
                     }
-                    // LIFO deletion of sites rn+1..n restores the table exactly
-                    for (uint32_t i = rn + 1u + (uint32_t)lane; i <= n; i += 64u) table[sid[i]] = (Key)0;
-                    L_::unpack((Key)ekey, ex, ey, ez);
-                    n = rn;
-                    control = false;
-                    wave_fence();
+                    if (n == n_max) bt = true;
+                    else control = control_mode;
                 }
             }
-            // end of the tour (or abort): back to the empty walk
-            for (uint32_t i = 1u + (uint32_t)lane; i <= n; i += 64u) table[sid[i]] = (Key)0;
-            wave_fence();
+            if (bt) {
+                // ---- resume the most recent pending copy, or end the tour ----
+                if (sp == 0u) break;
+                const uint32_t rn = top_n;
+                w = top_w;
+                const uint64_t ekey = top_key;
+                top_rem -= 1u;
+                if (top_rem == 0u) {
+                    sp -= 1u;
+                    if (sp > 0u) {
+                        const StackEntry e = stk[sp - 1];
+                        top_n = ufirst(e.n);
+                        top_rem = ufirst(e.remaining);
+                        top_w = XF{e.m, e.e};
+                        top_key = ufirst64(e.key);
+                    }
+                }
+                // LIFO deletion of sites rn+1..n restores the table exactly
+                for (uint32_t i = rn + 1u + (uint32_t)lane; i <= n; i += 64u) table[sid[i]] = (Key)0;
+                L_::unpack((Key)ekey, ex, ey, ez);
+                n = rn;
+                control = false;
+                wave_fence();
+            }
         }
-        if (lane == 0) Ls[0] = rec0;
+        // end of the tour (or abort): back to the empty walk
+        for (uint32_t i = 1u + (uint32_t)lane; i <= n; i += 64u) table[sid[i]] = (Key)0;
         wave_fence();
-        for (uint32_t i = (uint32_t)lane; i <= n_max; i += 64u) Lrow[i] = Ls[i];
-        if (lane == 0) {
-            if (abort) atomicOr(&A.ctrl[CTRL_ERR], ERR_CAP);
-            uint64_t* sr = A.stats + (size_t)s * STATS_WORDS;
-            A.t[s] = t0 + c_tours;
-            A.m[s] = m;
-            sr[ST_STEPS] += c_steps;
-            sr[ST_TOURS] += c_tours;
-            if (c_maxd > sr[ST_MAXDEPTH]) sr[ST_MAXDEPTH] = c_maxd;
-            sr[ST_DIGEST] = digest;
-            if (abort) sr[ST_CAPPED] = 1;
+    }
+    if (lane == 0) Ls[0] = rec0;
+    wave_fence();
+    for (uint32_t i = (uint32_t)lane; i <= n_max; i += 64u) Lrow[i] = Ls[i];
+    if (lane == 0) {
+        if (abort) atomicOr(&P.ctrl[CTRL_ERR], ERR_CAP);
+        uint64_t* sr = P.stats + (size_t)s * STATS_WORDS;
+        P.t[s] = t0 + c_tours;
+        P.m[s] = m;
+        sr[ST_STEPS] += c_steps;
+        sr[ST_TOURS] += c_tours;
+        if (c_maxd > sr[ST_MAXDEPTH]) sr[ST_MAXDEPTH] = c_maxd;
+        sr[ST_DIGEST] = digest;
+        if (abort) sr[ST_CAPPED] = 1;
+    }
+    if (lane == ST_EVENTS || lane == ST_ENRICH || lane == ST_COPIES || lane == ST_PRUNES ||
+        lane == ST_TRAPS)
+        P.stats[(size_t)s * STATS_WORDS + lane] += cv;
+}
+
+// Persistent launch over (problem, sequence) items of one or many problems:
+// each wavefront takes the next item from a device queue until none is left.
+// A problem alone is a batch of one, so a problem's bits do not depend on what
+// else shares the launch.
+__global__ void __launch_bounds__(64) batch_kernel(BatchArgs B) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    const int lane = (int)threadIdx.x;
+    for (;;) {
+        uint32_t got = 0u;
+        if (lane == 0) got = atomicAdd(B.queue, 1u);
+        const uint32_t item = ufirst(__shfl(got, 0, 64));
+        if (item >= B.total_items) break;
+        // the problem owning the item: entries are sorted by their first item
+        LaunchEntry E = B.single;
+        if (B.count > 1) {
+            uint32_t lo = 0, hi = B.count - 1;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi + 1) >> 1;
+                if (B.entries[mid].first_item <= item) lo = mid;
+                else hi = mid - 1;
+            }
+            E = B.entries[lo];
         }
-        if (lane == ST_EVENTS || lane == ST_ENRICH || lane == ST_COPIES || lane == ST_PRUNES ||
-            lane == ST_TRAPS)
-            A.stats[(size_t)s * STATS_WORDS + lane] += cv;
+        const ProblemDesc P = *E.desc;
+        const uint32_t s = item - E.first_item;
+        if (P.dim == 2) walk_sequence<2>(P, E.tours, E.step_cap, s, lds);
+        else walk_sequence<3>(P, E.tours, E.step_cap, s, lds);
     }
 }
 
@@ -1017,15 +1045,17 @@ hipError_t launch_init_state(uint64_t* stats, uint32_t N, void* zero_base, size_
         default: break;                                                 \
     }
 
+hipError_t launch_batch(const BatchArgs& b, uint32_t workgroups, uint32_t lds_bytes, hipStream_t s) {
+    hipLaunchKernelGGL(batch_kernel, dim3(workgroups), dim3(64), lds_bytes, s, b);
+    return hipGetLastError();
+}
+
+hipError_t batch_occupancy(uint32_t lds_bytes, int* blocks_per_cu) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_kernel, 64, lds_bytes);
+}
+
 hipError_t launch_run(const RunArgs& a, uint32_t dim, uint32_t team_lanes, uint32_t workgroups,
                       uint32_t lds_bytes, hipStream_t s) {
-    if (team_lanes == 64) {
-        if (dim == 2)
-            hipLaunchKernelGGL(walker_kernel<2>, dim3(workgroups), dim3(64), lds_bytes, s, a, a.G, a.L);
-        else
-            hipLaunchKernelGGL(walker_kernel<3>, dim3(workgroups), dim3(64), lds_bytes, s, a, a.G, a.L);
-        return hipGetLastError();
-    }
     if (dim == 2) {
         PPERM_TS_SWITCH(2, launch_run_t, a, workgroups, lds_bytes, s)
     } else if (dim == 3) {
@@ -1036,11 +1066,7 @@ hipError_t launch_run(const RunArgs& a, uint32_t dim, uint32_t team_lanes, uint3
 
 hipError_t run_kernel_lds_ok(uint32_t dim, uint32_t team_lanes, uint32_t lds_bytes,
                              int* blocks_per_cu) {
-    if (team_lanes == 64) {
-        if (dim == 2)
-            return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, walker_kernel<2>, 64, lds_bytes);
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, walker_kernel<3>, 64, lds_bytes);
-    }
+    if (team_lanes == 64) return batch_occupancy(lds_bytes, blocks_per_cu);
     if (dim == 2) {
         PPERM_TS_SWITCH(2, occupancy_t, lds_bytes, blocks_per_cu)
     } else if (dim == 3) {

@@ -122,3 +122,48 @@ class ParallelFlatPERM:
             self.close()
         except Exception:
             pass
+
+
+class Batch:
+    """Batched launches over many ParallelFlatPERM problems on one device.
+
+    Every problem in a call runs its own number of tours, exactly as its own
+    run_tours would; the bits of each problem do not depend on the others."""
+
+    def __init__(self, max_problems, device=None, stream=None):
+        lib = _abi.load()
+        self.device = torch.device(device if device is not None else "cuda")
+        nbytes = ctypes.c_size_t()
+        _abi.check(lib.pperm_batch_workspace_bytes(max_problems, ctypes.byref(nbytes)),
+                   "pperm_batch_workspace_bytes")
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        self.max_problems = max_problems
+        self._lib = lib
+
+    def run_tours(self, problems, tours_each):
+        """problems[i] runs tours_each[i] more tours (0: skipped)."""
+        count = len(problems)
+        if count > self.max_problems:
+            raise ValueError("more problems than the batch workspace was sized for")
+        ctxs = (ctypes.c_void_p * count)(*[p._ctx for p in problems])
+        tours = (ctypes.c_uint32 * count)(*[int(t) for t in tours_each])
+        _abi.check(self._lib.pperm_run_batch(ctxs, count, tours, ctypes.c_void_p(self.workspace.data_ptr()),
+                                             self.workspace.numel(),
+                                             ctypes.c_void_p(self.stream.cuda_stream)),
+                   "pperm_run_batch")
+
+
+def run_schedules(problems, schedules, batch=None):
+    """Run each problem through its own epoch schedule (tours per epoch, a merge
+    after each), all problems of an epoch index in one batched launch."""
+    if batch is None:
+        batch = Batch(len(problems), device=problems[0].device)
+    for i in range(max(len(s) for s in schedules)):
+        tours = [s[i] if i < len(s) else 0 for s in schedules]
+        batch.run_tours(problems, tours)
+        for p, t in zip(problems, tours):
+            if t:
+                p.merge_epoch()
+    return batch

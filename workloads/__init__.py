@@ -35,16 +35,19 @@ class Problem:
         """Tours per sequence of each epoch (one merge after each).
 
         With warm-up the first tours_per_epoch tours are split into epochs of
-        1, 1, 2, 4, ..., tours_per_epoch / 2 tours, so that the sequences start
-        sharing their running averages after their first tour; the remaining
-        epochs have tours_per_epoch tours.  The total is epochs * tours_per_epoch
-        either way."""
+        1, 1, 2, 4, ... tours (doubling while the running total stays within
+        tours_per_epoch) and one epoch of the remainder, so that the sequences
+        start sharing their running averages after their first tour; the
+        remaining epochs have tours_per_epoch tours.  The total is
+        epochs * tours_per_epoch either way."""
         T = self.tours_per_epoch
-        if not self.warmup or T == 1 or (T & (T - 1)) != 0:
+        if not self.warmup or T == 1:
             return [T] * self.epochs
         head = [1]
-        while sum(head) < T:
+        while 2 * sum(head) <= T:
             head.append(sum(head))
+        if sum(head) < T:
+            head.append(T - sum(head))
         return head + [T] * (self.epochs - 1)
 
     def as_dict(self):
