@@ -37,6 +37,7 @@ WORKLOADS = {
     "parallel3d": workloads.PARALLEL_3D,
     "plain2d": workloads.PLAIN_2D,
     "batched": None,          # the 256-problem mix, see run_batched()
+    "served": None,           # the Poisson job stream, see run_served()
 }
 
 
@@ -78,6 +79,12 @@ def main():
     ap.add_argument("--walks-per-wave", type=int, default=0)
     ap.add_argument("--hash-slots", type=int, default=0)
     ap.add_argument("--problems", type=int, default=0, help="batched: use the first P problems of the mix")
+    ap.add_argument("--serve-duration", type=float, default=60.0, help="served: arrival window (s)")
+    ap.add_argument("--serve-rate", type=float, default=50.0, help="served: arrivals per second")
+    ap.add_argument("--serve-cap", type=int, default=4096, help="served: tour cap per job")
+    ap.add_argument("--serve-target", type=float, default=1e-3, help="served: relative-error target")
+    ap.add_argument("--serve-pool-gib", type=float, default=8.0)
+    ap.add_argument("--serve-max-sequences", type=int, default=32768)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
 
@@ -88,6 +95,9 @@ def main():
 
     if args.workload == "batched":
         run_batched(args)
+        return
+    if args.workload == "served":
+        run_served(args)
         return
 
     import numpy as np
@@ -308,6 +318,131 @@ def run_batched(args, plain_budget_s=40.0):
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline_mix(mix)
+    print(json.dumps(line), flush=True)
+
+
+def run_served(args, plain_budget_s=30.0):
+    """A Poisson stream of sampling jobs served with continuous batching: jobs
+    arrive in real time, are admitted by workspace footprint and active
+    sequences, advance one epoch per server step together with every other
+    active job, and retire at the first merge that meets their stop rule."""
+    import numpy as np
+    import torch
+    from paper_2002_03000_amd import Server
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    jobs = workloads.served_arrivals(rate_per_s=args.serve_rate, duration_s=args.serve_duration,
+                                     target_rel_err=args.serve_target, tour_cap=args.serve_cap)
+    pool = int(args.serve_pool_gib * (1 << 30))
+
+    # warm-up: a few small jobs through their own server
+    warm = Server(64 << 20, 4096)
+    for j in jobs[:4]:
+        warm.submit(j.problem.dim, min(j.problem.n_max, 100), j.problem.n_sequences, j.problem.seed + 99,
+                    j.problem.tours_per_epoch, 4096, 0.0, stream_id=j.problem.stream)
+    while warm.counts()[:2] != (0, 0):
+        warm.step()
+    warm.close()
+    torch.cuda.synchronize()
+
+    srv = Server(pool, args.serve_max_sequences)
+    arrival, index = {}, {}
+    lat = np.full(len(jobs), np.nan)
+    steps_done, step_events, active_sum, n_steps = 0, [], 0, 0
+    stops = {1: 0, 2: 0}
+    nxt = 0
+    t0 = time.perf_counter()
+    last = t0
+    while True:
+        now = time.perf_counter() - t0
+        while nxt < len(jobs) and jobs[nxt].arrival_s <= now:
+            j = jobs[nxt]
+            jid = srv.submit_problem(j.problem, j.tour_cap, j.target_rel_err)
+            arrival[jid], index[jid] = j.arrival_s, nxt
+            nxt += 1
+        q, a, _ = srv.counts()
+        if q == 0 and a == 0:
+            if nxt >= len(jobs):
+                break
+            time.sleep(max(0.0, jobs[nxt].arrival_s - now))
+            continue
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        fin = srv.step()
+        ev1.record(stream)
+        step_events.append((ev0, ev1))
+        active_sum += a
+        n_steps += 1
+        tnow = time.perf_counter() - t0
+        for jid in fin:
+            info = srv.info(jid)
+            if info["state"] != "done":
+                raise RuntimeError(f"served job {index[jid]} failed: {info}")
+            lat[index[jid]] = tnow - arrival[jid]
+            steps_done += info["steps"]
+            stops[info["stop"]] = stops.get(info["stop"], 0) + 1
+            srv.release(jid)
+        if time.perf_counter() - last > 10:
+            last = time.perf_counter()
+            _log(f"served: t={tnow:.1f} s, {nxt}/{len(jobs)} arrived, {int(np.sum(~np.isnan(lat)))} done, "
+                 f"{q} queued, {a} active")
+    elapsed = time.perf_counter() - t0
+    srv.close()
+    gpu_ms = sum(a.elapsed_time(b) for a, b in step_events)
+    value = steps_done / elapsed
+
+    # the plain path on the same jobs, one at a time (same results by construction)
+    t1 = time.perf_counter()
+    plain_steps, plain_jobs = 0, 0
+    for j in jobs:
+        one = Server(256 << 20, 4096)
+        jid = one.submit_problem(j.problem, j.tour_cap, j.target_rel_err)
+        while one.info(jid)["state"] not in ("done", "failed"):
+            one.step()
+        plain_steps += one.info(jid)["steps"]
+        one.close()
+        plain_jobs += 1
+        if time.perf_counter() - t1 > plain_budget_s:
+            break
+    plain_dt = time.perf_counter() - t1
+
+    ops = (ALG_OPS_PER_STEP[2] + ALG_OPS_PER_STEP[3]) / 2
+    achieved = steps_done / (gpu_ms / 1e3) * ops / 1e12
+    line = {
+        "metric": "walk-steps/s (parallel flatPERM, 1 GPU)",
+        "value": value,
+        "unit": "walk-steps/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": elapsed * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (Poisson arrivals, seed 5; walks grown from parameters)",
+        "config": {"workload": f"served: Poisson {args.serve_rate}/s for {args.serve_duration} s "
+                               f"({len(jobs)} jobs), d in {{2,3}}, n_max in [50,2000], N=256, T=16, "
+                               f"stop at rel. err <= {args.serve_target} or {args.serve_cap} tours",
+                   "jobs": len(jobs), "tour_cap": args.serve_cap, "target_rel_err": args.serve_target,
+                   "pool_bytes": pool, "max_active_sequences": args.serve_max_sequences},
+        "latency_s": {"p50": float(np.nanpercentile(lat, 50)), "p99": float(np.nanpercentile(lat, 99)),
+                      "max": float(np.nanmax(lat))},
+        "server": {"steps": n_steps, "mean_active_jobs": active_sum / max(1, n_steps),
+                   "stopped_by_target": stops.get(1, 0), "stopped_by_cap": stops.get(2, 0),
+                   "gpu_busy_frac": gpu_ms / 1e3 / elapsed},
+        "plain_path": {"value": plain_steps / plain_dt, "unit": "walk-steps/s",
+                       "sample": f"the first {plain_jobs} jobs one at a time ({plain_steps} walk-steps) "
+                                 f"in {plain_dt:.2f} s"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
+                     "frac": achieved / ALU_PEAK_TOPS, "traffic": None,
+                     "kernel": "server step (batch_kernel + merges)", "avg_launch_ms": gpu_ms / max(1, n_steps),
+                     "alg_ops_per_step": ops},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_mix([j.problem for j in jobs])
     print(json.dumps(line), flush=True)
 
 

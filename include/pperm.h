@@ -66,8 +66,14 @@ typedef struct pperm_config {
     uint32_t step_cap;        /* growth steps per sequence per pperm_run_tours call after
                                  which the sequence stops with PPERM_EOVERFLOW; 0 = the
                                  watchdog default min(2^31, 4096 * tours * (n_max + 1))  */
-    uint32_t flags;           /* reserved, must be 0                                      */
+    uint32_t flags;           /* 0 or PPERM_FLAG_GROUP_STATS                               */
 } pperm_config;
+
+/* Keep 16 group sums of the weights recorded at n_max (sequence s in group
+ * s mod 16), cumulative over merged epochs, for pperm_error_estimate.  Adds one
+ * small kernel to every merge; never changes any other result. */
+#define PPERM_FLAG_GROUP_STATS  1u
+#define PPERM_GROUPS            16u
 
 /* Per-sequence counters, cumulative over the context's life (10 x uint64 each). */
 typedef struct pperm_seq_stats {
@@ -103,6 +109,7 @@ typedef struct pperm_layout {
     uint64_t total;      /* bytes used                                                    */
     uint32_t row;        /* n1p: records per row of G/HG/L (>= n_max + 1)                */
     uint32_t stack_slots;/* walks that can be in flight at once                           */
+    uint64_t groups;     /* 16 records (group sums at n_max) then 16 u64 (group tours)  */
 } pperm_layout;
 
 typedef struct pperm_ctx pperm_ctx;
@@ -160,6 +167,17 @@ int pperm_run_batch(pperm_ctx* const* ctxs, size_t count, const uint32_t* tours_
  * ERANGE / EOVERFLOW (raised by a kernel since the last check), EDEVICE. */
 int pperm_estimates(pperm_ctx* ctx, double* log_cn, uint64_t* hist, uint64_t* tours, size_t len);
 
+/* Synchronise and estimate the relative error of the estimate of c_{n_max}
+ * from the 16 sequence groups (needs PPERM_FLAG_GROUP_STATS).  Each group k has
+ * the cumulative sum A_k of the weights its sequences recorded at n_max (added
+ * in increasing s within an epoch, then to the running total) and its tour
+ * count C_k; its estimate is g_k = A_k / C_k (eqn (4) restricted to the group).
+ * *rel_err = sd(g) / (4 mean(g)), the standard error of the mean of 16 groups
+ * relative to that mean (sample standard deviation, 15 degrees of freedom);
+ * +inf while a group has no tour or no weight at n_max.  log_groups (16 entries,
+ * may be NULL) receives log g_k.  Errors: EINVAL (flag not set), EDEVICE. */
+int pperm_error_estimate(pperm_ctx* ctx, double* rel_err, double* log_groups);
+
 /* Synchronise and copy the per-sequence counters into `out` (N entries). */
 int pperm_sequence_stats(pperm_ctx* ctx, pperm_seq_stats* out, size_t count);
 
@@ -176,6 +194,90 @@ int pperm_launch_shape(const pperm_ctx* ctx, uint32_t* walks_per_wave, uint32_t*
 
 /* Destroy a context (does not free the caller's workspace). */
 int pperm_destroy(pperm_ctx* ctx);
+
+/* ---- serving: continuous batching of sampling jobs ---------------------------
+ * A server owns a device memory pool (caller-owned, carved by a first-fit
+ * allocator) and a FIFO of submitted jobs.  Each pperm_server_step admits queued
+ * jobs in arrival order while their workspace (pperm_workspace_bytes) fits in
+ * the pool and the active sequences stay within max_active_sequences, runs the
+ * next epoch of every active job in one pperm_run_batch, merges each, and
+ * retires every job whose stop rule holds after that merge.  A job's results
+ * depend only on its own description, never on what else is served with it.
+ * Not thread-safe. */
+typedef struct pperm_server pperm_server;
+
+typedef struct pperm_job {
+    uint32_t struct_size;      /* sizeof(pperm_job)                                       */
+    uint32_t dim;              /* 2 or 3                                                  */
+    uint32_t n_max;
+    uint32_t n_sequences;      /* N >= 16 for the relative-error stop rule                */
+    uint64_t seed;
+    uint32_t mode;             /* PPERM_SHARED / PPERM_INDEPENDENT / PPERM_ROSENBLUTH     */
+    uint32_t stream_id;
+    uint32_t tours_per_epoch;  /* T >= 1                                                  */
+    uint32_t warmup;           /* 1: first epochs of 1, 1, 2, 4, ... tours (doubling while
+                                  the total stays within T) and the remainder, then T      */
+    double target_rel_err;     /* stop at the first merge with pperm_error_estimate <= this
+                                  (0: no such stop)                                       */
+    uint64_t tour_cap;         /* stop at the first merge where the pooled tours M reach
+                                  this (M summed over sequences in PPERM_INDEPENDENT mode) */
+} pperm_job;
+
+#define PPERM_JOB_QUEUED  0u
+#define PPERM_JOB_ACTIVE  1u
+#define PPERM_JOB_DONE    2u
+#define PPERM_JOB_FAILED  3u
+
+typedef struct pperm_job_info {
+    uint32_t state;            /* PPERM_JOB_*                                             */
+    int32_t error;             /* the error that failed the job (PPERM_JOB_FAILED)        */
+    uint32_t epochs;           /* epochs run                                              */
+    uint32_t stop;             /* 1 stopped by the error target, 2 by the tour cap        */
+    uint64_t tours;            /* pooled tours M                                          */
+    uint64_t steps;            /* walk-steps                                              */
+    double rel_err;            /* the last error estimate                                 */
+    uint64_t workspace_bytes;  /* its share of the pool while active                      */
+} pperm_job_info;
+
+/* Create a server on the current device.  d_pool: caller-owned device memory,
+ * 256-byte aligned, pool_bytes long, outliving the server; all device work goes
+ * to hip_stream.  Errors: EINVAL (pool too small for the batch scratch). */
+int pperm_server_create(void* d_pool, size_t pool_bytes, uint32_t max_active_sequences,
+                        void* hip_stream, pperm_server** out);
+
+/* Queue a job; *id receives its id (1, 2, ...).  The job is validated here
+ * (EINVAL for a bad description or one that can never fit the pool). */
+int pperm_server_submit(pperm_server* srv, const pperm_job* job, uint64_t* id);
+
+/* One scheduling step (admit, one batched epoch, merges, stop rules); writes
+ * the ids of the jobs retired by this step into finished[0 .. cap) and their
+ * number into *n_finished (may exceed cap; the rest are still retired).
+ * Synchronises.  A job whose own calls fail is retired as PPERM_JOB_FAILED;
+ * the step itself fails only for device errors (EDEVICE). */
+int pperm_server_step(pperm_server* srv, uint64_t* finished, size_t cap, size_t* n_finished);
+
+/* State and counters of a job (EINVAL for an unknown or released id). */
+int pperm_server_info(pperm_server* srv, uint64_t id, pperm_job_info* info);
+
+/* The estimates of a retired job, as pperm_estimates (len >= n_max + 1; hist
+ * may be NULL).  ESTATE if the job is not done. */
+int pperm_server_result(pperm_server* srv, uint64_t id, double* log_cn, uint64_t* hist,
+                        size_t len);
+
+/* Forget a retired job's results. */
+int pperm_server_release(pperm_server* srv, uint64_t id);
+
+/* Jobs waiting and active, and the pool bytes in use. */
+int pperm_server_counts(pperm_server* srv, uint32_t* queued, uint32_t* active, uint64_t* pool_used);
+
+/* Destroy the server and every job it still holds (does not free the pool). */
+int pperm_server_destroy(pperm_server* srv);
+
+/* The server's pool allocator run on a script, host only (for checking it):
+ * ops[i] > 0 allocates ops[i] bytes, ops[i] < 0 frees the block returned by
+ * operation -ops[i] - 1.  offsets[i] receives the offset of each allocation
+ * (-1 when it does not fit, 0 for a free).  Returns the bytes still in use. */
+int64_t pperm_pool_script(uint64_t pool_bytes, const int64_t* ops, size_t count, int64_t* offsets);
 
 /* Static description of an error code, and the text of the last HIP error. */
 const char* pperm_strerror(int code);

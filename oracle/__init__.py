@@ -11,6 +11,7 @@ The arithmetic lives in C (pperm_oracle.c, saw_enum.c); this module only
 marshals numpy arrays into it.
 """
 import ctypes
+import math
 import os
 
 import numpy as np
@@ -28,6 +29,7 @@ STATS_FIELDS = ("steps", "events", "enrich", "copies", "prunes", "traps",
                 "tours", "max_depth", "digest", "capped")
 STATS_DTYPE = np.dtype([(f, np.uint64) for f in STATS_FIELDS])
 # extended-range number m * 2^e (m in [0.5, 1), or m = 0 and e = 0)
+GROUPS = 16          # sequence groups of the relative-error estimate (s mod 16)
 XF_DTYPE = np.dtype([("m", np.float64), ("e", np.int32), ("pad", np.uint32)])
 
 
@@ -73,6 +75,7 @@ def lib():
         L.orc_run_epoch.restype = ctypes.c_int
         L.orc_merge.argtypes = [ctypes.POINTER(_Params), ctypes.c_int64, vp, u32p, u32p,
                                 vp, u64p, u64p]
+        L.orc_group_sums.argtypes = [ctypes.POINTER(_Params), ctypes.c_int64, vp, u32p, vp, u64p]
         L.orc_log_estimates.argtypes = [ctypes.c_int64, vp, ctypes.c_uint64, dblp]
         L.orc_plain_recursive.argtypes = [ctypes.POINTER(_Params), ctypes.c_uint32, vp, u32p]
         L.orc_plain_recursive.restype = ctypes.c_int
@@ -169,7 +172,7 @@ class Oracle:
     """Parallel flatPERM state and its epoch schedule (run / merge calls)."""
 
     def __init__(self, dim, n_max, n_sequences, seed, mode=MODE_SHARED, stream=0,
-                 step_cap=0, threads=0):
+                 step_cap=0, threads=0, group_stats=False):
         self.params = _Params(dim, mode, n_max, seed & 0xFFFFFFFFFFFFFFFF, stream, 0, step_cap,
                               n_sequences)
         self.dim, self.n_max, self.N, self.mode = dim, n_max, n_sequences, mode
@@ -185,6 +188,9 @@ class Oracle:
         self.m = np.zeros(n_sequences, dtype=np.uint32)
         self.stats = np.zeros(n_sequences, dtype=STATS_DTYPE)
         lib().orc_stats_init(self.stats.ctypes.data, n_sequences)
+        self.group_stats = group_stats
+        self.gsum = np.zeros(GROUPS, dtype=XF_DTYPE)
+        self.gtours = np.zeros(GROUPS, dtype=np.uint64)
 
     def run_tours(self, tours, ids=None):
         """Every sequence (or only `ids`) runs `tours` more tours. Returns True if capped."""
@@ -200,6 +206,10 @@ class Oracle:
         return bool(rc)
 
     def merge_epoch(self):
+        if self.group_stats:
+            lib().orc_group_sums(ctypes.byref(self.params), self.N, self.L.ctypes.data,
+                                 _ptr(self.m, ctypes.c_uint32), self.gsum.ctypes.data,
+                                 _ptr(self.gtours, ctypes.c_uint64))
         lib().orc_merge(ctypes.byref(self.params), self.N, self.L.ctypes.data,
                         _ptr(self.H, ctypes.c_uint32), _ptr(self.m, ctypes.c_uint32),
                         self.G.ctypes.data, _ptr(self.HG, ctypes.c_uint64),
@@ -216,6 +226,16 @@ class Oracle:
         out = np.zeros(self.n_max + 1)
         lib().orc_log_estimates(self.n_max, self.G.ctypes.data, int(self.MG[0]), _ptr(out, ctypes.c_double))
         return out
+
+    def error_estimate(self):
+        """Relative error estimate of c_{n_max} from the 16 group sums: the
+        sample standard deviation of the group averages A_k / C_k over 4 times
+        their mean (+inf while a group is empty or has no weight at n_max)."""
+        if np.any(self.gtours == 0) or np.any(self.gsum["m"] == 0.0):
+            return math.inf
+        lg = xf_log(self.gsum) - np.log(self.gtours.astype(np.float64))
+        x = np.exp(lg - lg.max())
+        return float(np.std(x, ddof=1) / (4.0 * np.mean(x)))
 
     def walk_steps(self):
         return int(self.stats["steps"].sum())

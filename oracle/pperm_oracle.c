@@ -603,6 +603,27 @@ void orc_merge(const orc_params* P, int64_t N, orc_xf* L, uint32_t* H, uint32_t*
     memset(m, 0, sizeof(uint32_t) * (size_t)N);
 }
 
+/* Group sums for the relative-error estimate of c_{n_max}: sequences fall in
+ * 16 groups by s mod 16.  Group k adds, from zero and in increasing s, the
+ * weights its sequences recorded at n_max in the open epoch, then adds that to
+ * its running total; its tour count grows by its sequences' m.  Called before
+ * orc_merge (which zeroes L and m). */
+void orc_group_sums(const orc_params* P, int64_t N, const orc_xf* L, const uint32_t* m,
+                    orc_xf* gsum, uint64_t* gtours)
+{
+    const int64_t n1 = P->n_max + 1;
+    for (int64_t k = 0; k < 16; ++k) {
+        orc_xf acc = { 0.0, 0, 0 };
+        uint64_t tours = 0;
+        for (int64_t s = k; s < N; s += 16) {
+            acc = orc_xf_add(acc, L[s * n1 + P->n_max]);
+            tours += m[s];
+        }
+        gsum[k] = orc_xf_add(gsum[k], acc);
+        gtours[k] += tours;
+    }
+}
+
 /* Estimates (eqn (4)): log c_n = ln G_n.m + G_n.e ln 2 - ln M. */
 void orc_log_estimates(int64_t n_max, const orc_xf* G, uint64_t MG, double* out)
 {

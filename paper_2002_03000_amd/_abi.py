@@ -13,6 +13,10 @@ PPERM_INDEPENDENT = 1
 PPERM_ROSENBLUTH = 2
 MODES = {"shared": PPERM_SHARED, "independent": PPERM_INDEPENDENT, "rosenbluth": PPERM_ROSENBLUTH}
 
+FLAG_GROUP_STATS = 1
+GROUPS = 16
+JOB_QUEUED, JOB_ACTIVE, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
+
 ERRORS = {0: "PPERM_OK", -1: "PPERM_EINVAL", -2: "PPERM_ENOMEM", -3: "PPERM_EDEVICE",
           -4: "PPERM_ESTATE", -5: "PPERM_ERANGE", -6: "PPERM_EOVERFLOW"}
 
@@ -37,7 +41,23 @@ class SeqStats(ctypes.Structure):
 class Layout(ctypes.Structure):
     _fields_ = [(f, ctypes.c_uint64) for f in ("G", "HG", "MG", "L", "m", "t", "stats",
                                                 "stack", "scratch", "ctrl", "total")] + \
-               [("row", ctypes.c_uint32), ("stack_slots", ctypes.c_uint32)]
+               [("row", ctypes.c_uint32), ("stack_slots", ctypes.c_uint32), ("groups", ctypes.c_uint64)]
+
+
+class Job(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("dim", ctypes.c_uint32),
+                ("n_max", ctypes.c_uint32), ("n_sequences", ctypes.c_uint32),
+                ("seed", ctypes.c_uint64), ("mode", ctypes.c_uint32),
+                ("stream_id", ctypes.c_uint32), ("tours_per_epoch", ctypes.c_uint32),
+                ("warmup", ctypes.c_uint32), ("target_rel_err", ctypes.c_double),
+                ("tour_cap", ctypes.c_uint64)]
+
+
+class JobInfo(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_uint32), ("error", ctypes.c_int32),
+                ("epochs", ctypes.c_uint32), ("stop", ctypes.c_uint32),
+                ("tours", ctypes.c_uint64), ("steps", ctypes.c_uint64),
+                ("rel_err", ctypes.c_double), ("workspace_bytes", ctypes.c_uint64)]
 
 
 # Every symbol include/pperm.h declares, with its ctypes signature.
@@ -51,12 +71,22 @@ SIGNATURES = {
     "pperm_batch_workspace_bytes": (_int, [_sz, _c.POINTER(_sz)]),
     "pperm_run_batch": (_int, [_c.POINTER(_vp), _sz, _c.POINTER(_u32), _vp, _sz, _vp]),
     "pperm_estimates": (_int, [_vp, _c.POINTER(_c.c_double), _c.POINTER(_u64), _c.POINTER(_u64), _sz]),
+    "pperm_error_estimate": (_int, [_vp, _c.POINTER(_c.c_double), _c.POINTER(_c.c_double)]),
     "pperm_sequence_stats": (_int, [_vp, _c.POINTER(SeqStats), _sz]),
     "pperm_stats": (_int, [_vp, _c.POINTER(SeqStats)]),
     "pperm_sync": (_int, [_vp]),
     "pperm_layout_of": (_int, [_vp, _c.POINTER(Layout)]),
     "pperm_launch_shape": (_int, [_vp, _c.POINTER(_u32), _c.POINTER(_u32), _c.POINTER(_u32)]),
     "pperm_destroy": (_int, [_vp]),
+    "pperm_server_create": (_int, [_vp, _sz, _u32, _vp, _c.POINTER(_vp)]),
+    "pperm_server_submit": (_int, [_vp, _c.POINTER(Job), _c.POINTER(_u64)]),
+    "pperm_server_step": (_int, [_vp, _c.POINTER(_u64), _sz, _c.POINTER(_sz)]),
+    "pperm_server_info": (_int, [_vp, _u64, _c.POINTER(JobInfo)]),
+    "pperm_server_result": (_int, [_vp, _u64, _c.POINTER(_c.c_double), _c.POINTER(_u64), _sz]),
+    "pperm_server_release": (_int, [_vp, _u64]),
+    "pperm_server_counts": (_int, [_vp, _c.POINTER(_u32), _c.POINTER(_u32), _c.POINTER(_u64)]),
+    "pperm_server_destroy": (_int, [_vp]),
+    "pperm_pool_script": (_c.c_int64, [_u64, _c.POINTER(_c.c_int64), _sz, _c.POINTER(_c.c_int64)]),
     "pperm_strerror": (_c.c_char_p, [_int]),
     "pperm_last_device_error": (_c.c_char_p, []),
 }

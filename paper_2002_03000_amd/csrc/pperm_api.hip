@@ -111,7 +111,7 @@ int validate(const pperm_config* c) {
     if (c->n_max < 1 || c->n_max > kMaxNmax) return PPERM_EINVAL;
     if (c->n_sequences < 1) return PPERM_EINVAL;
     if (c->mode > PPERM_ROSENBLUTH) return PPERM_EINVAL;
-    if (c->flags != 0) return PPERM_EINVAL;
+    if ((c->flags & ~PPERM_FLAG_GROUP_STATS) != 0) return PPERM_EINVAL;
     Shape sh;
     return resolve_shape(c, &sh);
 }
@@ -143,6 +143,7 @@ void compute_layout(const pperm_config* c, pperm_layout* L) {
     L->m = take(N * 4);
     L->t = take(N * 8);
     L->stats = take(N * STATS_WORDS * 8);
+    L->groups = take(GROUPS * (sizeof(SumRec) + 8));
     L->ctrl = take(CTRL_WORDS * 4 + sizeof(ProblemDesc));
     // private scratch, not zeroed: copy stacks, merge partials (records + counts, x2)
     L->stack = take(stack_slots * c->n_max * sizeof(StackEntry));
@@ -340,6 +341,11 @@ int pperm_merge_epoch(pperm_ctx* x) {
     SumRec* G = at<SumRec>(x, x->lay.G);
     uint64_t* HG = at<uint64_t>(x, x->lay.HG);
     uint64_t* MG = at<uint64_t>(x, x->lay.MG);
+    if (x->cfg.flags & PPERM_FLAG_GROUP_STATS) {
+        SumRec* gsum = at<SumRec>(x, x->lay.groups);
+        HIP_TRY(launch_group_sums(L, m, N, row, x->cfg.n_max, gsum,
+                                  reinterpret_cast<uint64_t*>(gsum + GROUPS), x->stream));
+    }
     if (x->cfg.mode == PPERM_INDEPENDENT) {
         HIP_TRY(launch_merge_independent(L, m, G, HG, MG, N, row, x->stream));
         x->merged_tours += x->open_tours;
@@ -593,6 +599,48 @@ int pperm_estimates(pperm_ctx* x, double* log_cn, uint64_t* hist, uint64_t* tour
         if (hist) hist[n] = HG[n];
     }
     if (tours) *tours = MG;
+    return PPERM_OK;
+}
+
+int pperm_error_estimate(pperm_ctx* x, double* rel_err, double* log_groups) {
+    if (!x || !rel_err) return PPERM_EINVAL;
+    if (!(x->cfg.flags & PPERM_FLAG_GROUP_STATS)) return PPERM_EINVAL;
+    struct {
+        SumRec sum[GROUPS];
+        uint64_t tours[GROUPS];
+    } g;
+    static_assert(sizeof(g) == GROUPS * (sizeof(SumRec) + 8), "group record layout");
+    HIP_TRY(hipMemcpyAsync(&g, at<unsigned char>(x, x->lay.groups), sizeof(g),
+                           hipMemcpyDeviceToHost, x->stream));
+    HIP_TRY(hipStreamSynchronize(x->stream));
+    const double ln2 = 0.69314718055994530942;
+    double lg[GROUPS];
+    bool defined = true;
+    double top = -INFINITY;
+    for (uint32_t k = 0; k < GROUPS; ++k) {
+        if (g.tours[k] == 0 || g.sum[k].m == 0.0) {
+            defined = false;
+            lg[k] = -INFINITY;
+        } else {
+            lg[k] = log(g.sum[k].m) + g.sum[k].e * ln2 - log((double)g.tours[k]);
+        }
+        if (lg[k] > top) top = lg[k];
+        if (log_groups) log_groups[k] = lg[k];
+    }
+    if (!defined) {
+        *rel_err = INFINITY;
+        return PPERM_OK;
+    }
+    // scale-free: the groups relative to the largest one
+    double xs[GROUPS], mean = 0.0;
+    for (uint32_t k = 0; k < GROUPS; ++k) {
+        xs[k] = exp(lg[k] - top);
+        mean += xs[k];
+    }
+    mean /= GROUPS;
+    double ss = 0.0;
+    for (uint32_t k = 0; k < GROUPS; ++k) ss += (xs[k] - mean) * (xs[k] - mean);
+    *rel_err = sqrt(ss / (GROUPS - 1)) / (4.0 * mean);
     return PPERM_OK;
 }
 

@@ -19,6 +19,7 @@ enum : uint32_t { CTRL_QUEUE = 0, CTRL_ERR = 1, CTRL_WORDS = 16 };
 enum : uint32_t { MODE_SHARED = 0, MODE_INDEPENDENT = 1, MODE_ROSENBLUTH = 2 };
 
 constexpr int STATS_WORDS = 10;
+constexpr uint32_t GROUPS = 16;   // sequence groups of the error estimate (s mod 16)
 enum : int { ST_STEPS = 0, ST_EVENTS, ST_ENRICH, ST_COPIES, ST_PRUNES, ST_TRAPS,
              ST_TOURS, ST_MAXDEPTH, ST_DIGEST, ST_CAPPED };
 
@@ -126,6 +127,8 @@ hipError_t launch_batch(const BatchArgs& b, uint32_t workgroups, uint32_t lds_by
 hipError_t batch_occupancy(uint32_t lds_bytes, int* blocks_per_cu);
 hipError_t launch_merge_counts(const uint32_t* m, uint32_t N, uint64_t* MG, uint32_t* zero_m,
                                hipStream_t s);
+hipError_t launch_group_sums(const SumRec* L, const uint32_t* m, uint32_t N, uint32_t row,
+                             uint32_t n_max, SumRec* gsum, uint64_t* gtours, hipStream_t s);
 hipError_t launch_merge_independent(SumRec* L, uint32_t* m, SumRec* G, uint64_t* HG, uint64_t* MG,
                                     uint32_t N, uint32_t row, hipStream_t s);
 

@@ -987,6 +987,30 @@ __global__ void __launch_bounds__(256) merge_independent_kernel(SumRec* L, uint3
     }
 }
 
+// Group sums for the error estimate: lane k < 16 folds the records at n_max of
+// sequences k, k + 16, k + 32, ... (in that order, from zero) and adds the
+// result to the group's running total; tours likewise.  Runs before the merge
+// that zeroes the records.
+__global__ void __launch_bounds__(64) group_sums_kernel(const SumRec* L, const uint32_t* m,
+                                                        uint32_t N, uint32_t row, uint32_t n_max,
+                                                        SumRec* gsum, uint64_t* gtours) {
+    const uint32_t k = threadIdx.x;
+    if (k >= GROUPS) return;
+    XF acc = {0.0, 0};
+    uint64_t tours = 0;
+    for (uint32_t s = k; s < N; s += GROUPS) {
+        acc = xf_add(acc, xf_of(L[(size_t)s * row + n_max]));
+        tours += m[s];
+    }
+    const XF g = xf_add(xf_of(gsum[k]), acc);
+    SumRec r;
+    r.m = g.m;
+    r.e = g.e;
+    r.h = 0u;
+    gsum[k] = r;
+    gtours[k] += tours;
+}
+
 __global__ void reset_ctrl_kernel(uint32_t* ctrl) {
     if (threadIdx.x == CTRL_QUEUE) ctrl[CTRL_QUEUE] = 0u;
 }
@@ -1084,6 +1108,12 @@ hipError_t launch_merge_pass(const MergeArgs& a, hipStream_t s) {
 hipError_t launch_merge_counts(const uint32_t* m, uint32_t N, uint64_t* MG, uint32_t* zero_m,
                                hipStream_t s) {
     hipLaunchKernelGGL(merge_counts_kernel, dim3(1), dim3(256), 0, s, m, N, MG, zero_m);
+    return hipGetLastError();
+}
+
+hipError_t launch_group_sums(const SumRec* L, const uint32_t* m, uint32_t N, uint32_t row,
+                             uint32_t n_max, SumRec* gsum, uint64_t* gtours, hipStream_t s) {
+    hipLaunchKernelGGL(group_sums_kernel, dim3(1), dim3(64), 0, s, L, m, N, row, n_max, gsum, gtours);
     return hipGetLastError();
 }
 

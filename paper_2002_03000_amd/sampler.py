@@ -19,11 +19,13 @@ class ParallelFlatPERM:
     """
 
     def __init__(self, dim, n_max, n_sequences, seed, mode="shared", stream_id=0,
-                 hash_slots=0, walks_per_wave=0, step_cap=0, device=None, stream=None):
+                 hash_slots=0, walks_per_wave=0, step_cap=0, group_stats=False, device=None,
+                 stream=None):
         lib = _abi.load()
         self.cfg = _abi.Config(ctypes.sizeof(_abi.Config), dim, n_max, n_sequences,
                                seed & 0xFFFFFFFFFFFFFFFF, _abi.MODES[mode], stream_id,
-                               hash_slots, walks_per_wave, step_cap, 0)
+                               hash_slots, walks_per_wave, step_cap,
+                               _abi.FLAG_GROUP_STATS if group_stats else 0)
         self.dim, self.n_max, self.N, self.mode = dim, n_max, n_sequences, mode
         self.device = torch.device(device if device is not None else "cuda")
         nbytes = ctypes.c_size_t()
@@ -62,6 +64,15 @@ class ParallelFlatPERM:
         return lc, hist, int(tours.value)
 
     # -- inspection -------------------------------------------------------------------
+    def error_estimate(self):
+        """(relative error estimate of c_{n_max} from 16 sequence groups, log group estimates)."""
+        rel = ctypes.c_double()
+        lg = np.zeros(_abi.GROUPS, dtype=np.float64)
+        _abi.check(self._lib.pperm_error_estimate(self._ctx, ctypes.byref(rel),
+                                                  lg.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+                   "pperm_error_estimate")
+        return rel.value, lg
+
     def sync(self):
         _abi.check(self._lib.pperm_sync(self._ctx), "pperm_sync")
 
@@ -101,14 +112,18 @@ class ParallelFlatPERM:
             "m": (torch.int32, (N,)),
             "t": (torch.int64, (N,)),
             "stats": (torch.int64, (N, len(_abi.STATS_FIELDS))),
+            "gsum": (torch.uint8, (_abi.GROUPS, 16)),
+            "gtours": (torch.int64, (_abi.GROUPS,)),
         }
         dt, shape = shapes[name]
-        off = getattr(lay, name)
+        off = {"gsum": lay.groups, "gtours": lay.groups + 16 * _abi.GROUPS}.get(name)
+        if off is None:
+            off = getattr(lay, name)
         nbytes = int(np.prod(shape)) * torch.tensor([], dtype=dt).element_size()
         return self.workspace[off:off + nbytes].view(dt).view(shape)
 
     def records(self, name):
-        """Host copy of the G or L records as a structured numpy array (m, e, h)."""
+        """Host copy of the G, L or gsum records as a structured numpy array (m, e, h)."""
         raw = self.view(name).cpu().numpy()
         return raw.reshape(raw.shape[:-1] + (16,)).view(self.RECORD_DTYPE)[..., 0]
 
@@ -167,3 +182,101 @@ def run_schedules(problems, schedules, batch=None):
             if t:
                 p.merge_epoch()
     return batch
+
+
+JOB_STATES = {_abi.JOB_QUEUED: "queued", _abi.JOB_ACTIVE: "active", _abi.JOB_DONE: "done",
+              _abi.JOB_FAILED: "failed"}
+
+
+class Server:
+    """Continuous batching of sampling jobs on one device (the library's server).
+
+    pool_bytes of device memory are allocated here (torch) and handed to the
+    library, which carves every admitted job's workspace out of it."""
+
+    def __init__(self, pool_bytes, max_active_sequences, device=None, stream=None):
+        lib = _abi.load()
+        self.device = torch.device(device if device is not None else "cuda")
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            self.pool = torch.empty(int(pool_bytes), dtype=torch.uint8, device=self.device)
+            srv = ctypes.c_void_p()
+            _abi.check(lib.pperm_server_create(ctypes.c_void_p(self.pool.data_ptr()), self.pool.numel(),
+                                               int(max_active_sequences),
+                                               ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(srv)),
+                       "pperm_server_create")
+        self._srv = srv
+        self._lib = lib
+        self._n_max = {}
+
+    def submit(self, dim, n_max, n_sequences, seed, tours_per_epoch, tour_cap, target_rel_err=0.0,
+               mode="shared", stream_id=0, warmup=True):
+        job = _abi.Job(ctypes.sizeof(_abi.Job), dim, n_max, n_sequences, seed & 0xFFFFFFFFFFFFFFFF,
+                       _abi.MODES[mode], stream_id, tours_per_epoch, 1 if warmup else 0,
+                       float(target_rel_err), int(tour_cap))
+        jid = ctypes.c_uint64()
+        _abi.check(self._lib.pperm_server_submit(self._srv, ctypes.byref(job), ctypes.byref(jid)),
+                   "pperm_server_submit")
+        self._n_max[jid.value] = n_max
+        return jid.value
+
+    def submit_problem(self, p, tour_cap, target_rel_err=0.0):
+        """Submit a workloads.Problem-like description."""
+        return self.submit(p.dim, p.n_max, p.n_sequences, p.seed, p.tours_per_epoch, tour_cap,
+                           target_rel_err, mode=p.mode, stream_id=p.stream, warmup=p.warmup)
+
+    def step(self, cap=4096):
+        """One scheduling step; the ids of the jobs it retired."""
+        out = (ctypes.c_uint64 * cap)()
+        nf = ctypes.c_size_t()
+        _abi.check(self._lib.pperm_server_step(self._srv, out, cap, ctypes.byref(nf)), "pperm_server_step")
+        if nf.value > cap:
+            raise RuntimeError("more jobs retired than the step buffer holds")
+        return [out[i] for i in range(nf.value)]
+
+    def info(self, jid):
+        inf = _abi.JobInfo()
+        _abi.check(self._lib.pperm_server_info(self._srv, jid, ctypes.byref(inf)), "pperm_server_info")
+        d = {f: getattr(inf, f) for f, _ in _abi.JobInfo._fields_}
+        d["state"] = JOB_STATES[d["state"]]
+        return d
+
+    def result(self, jid):
+        n1 = self._n_max[jid] + 1
+        lc = np.zeros(n1, dtype=np.float64)
+        hist = np.zeros(n1, dtype=np.uint64)
+        _abi.check(self._lib.pperm_server_result(self._srv, jid, lc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                                 hist.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), n1),
+                   "pperm_server_result")
+        return lc, hist
+
+    def release(self, jid):
+        _abi.check(self._lib.pperm_server_release(self._srv, jid), "pperm_server_release")
+        self._n_max.pop(jid, None)
+
+    def counts(self):
+        q, a, used = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint64()
+        _abi.check(self._lib.pperm_server_counts(self._srv, ctypes.byref(q), ctypes.byref(a), ctypes.byref(used)),
+                   "pperm_server_counts")
+        return q.value, a.value, used.value
+
+    def close(self):
+        if getattr(self, "_srv", None):
+            self._lib.pperm_server_destroy(self._srv)
+            self._srv = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pool_script(pool_bytes, ops):
+    """Run the server's pool allocator on a script (host only): see pperm_pool_script."""
+    lib = _abi.load()
+    ops = np.asarray(ops, dtype=np.int64)
+    offs = np.zeros(len(ops), dtype=np.int64)
+    used = lib.pperm_pool_script(int(pool_bytes), ops.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), len(ops),
+                                 offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    return offs, int(used)

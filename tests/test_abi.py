@@ -49,7 +49,7 @@ def _ws(cfg):
 
 
 @pytest.mark.parametrize("bad", [dict(dim=1), dict(dim=4), dict(n_max=0), dict(n_max=32767),
-                                 dict(n_sequences=0), dict(mode=3), dict(flags=1),
+                                 dict(n_sequences=0), dict(mode=3), dict(flags=2),
                                  dict(hash_slots=100), dict(hash_slots=128, n_max=100),
                                  dict(walks_per_wave=3), dict(walks_per_wave=32),
                                  dict(dim=3, walks_per_wave=16)])
@@ -78,3 +78,48 @@ def test_strerror_covers_every_code():
     lib = _abi.load()
     for code in _abi.ERRORS:
         assert lib.pperm_strerror(code).decode() != "unknown error"
+
+
+def _first_fit_model(cap, live, need):
+    """Lowest offset of a gap of at least `need` bytes among the live blocks."""
+    pos = 0
+    for off, size in sorted(live.items()):
+        if off - pos >= need:
+            return pos
+        pos = max(pos, off + size)
+    return pos if cap - pos >= need else -1
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_server_pool_allocator_first_fit_and_coalescing(seed):
+    import numpy as np
+    from paper_2002_03000_amd import pool_script
+    rng = np.random.default_rng(seed)
+    cap = 1 << 20
+    ops, live_ids = [], []
+    for i in range(400):
+        if live_ids and rng.random() < 0.45:
+            k = live_ids.pop(int(rng.integers(len(live_ids))))
+            ops.append(-(k + 1))
+        else:
+            ops.append(int(rng.integers(1, 60000)))
+            live_ids.append(i)
+    offs, used = pool_script(cap, ops)
+    live = {}
+    for i, op in enumerate(ops):
+        if op > 0:
+            need = (op + 255) // 256 * 256
+            expect = _first_fit_model(cap, live, need)
+            assert offs[i] == expect, (i, offs[i], expect)
+            if offs[i] >= 0:
+                assert offs[i] % 256 == 0
+                live[int(offs[i])] = need
+        else:
+            k = -op - 1
+            if offs[k] >= 0:
+                del live[int(offs[k])]
+    assert used == sum(live.values())
+    # freeing everything leaves one block: the whole pool fits again at offset 0
+    frees = [-(i + 1) for i, op in enumerate(ops) if op > 0 and offs[i] >= 0 and int(offs[i]) in live]
+    offs2, used2 = pool_script(cap, ops + frees + [cap])
+    assert used2 == cap and offs2[-1] == 0

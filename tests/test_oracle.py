@@ -357,3 +357,33 @@ def test_plain_flatperm_c1_budget():
         assert _cn_exact_ratio(o, n) == int(exact[n])
     flat = o.HG / float(o.MG[0])
     assert flat.min() > 0.9 and flat.max() < 1.1
+
+
+def test_group_sums_and_error_estimate_pinned():
+    # group k folds the weights recorded at n_max by sequences s = k (mod 16):
+    # against exact rational sums of the same records, the tour counts against
+    # the pooled count, and the estimate against the statistics module
+    import statistics
+    from fractions import Fraction
+    N, n_max = 40, 12
+    o = oracle.Oracle(2, n_max, N, 77, group_stats=True)
+    exact = [Fraction(0)] * 16
+    adds = [0] * 16
+    for T in (1, 1, 2, 4, 3):
+        o.run_tours(T)
+        for s in range(N):
+            rec = o.L[s, n_max]
+            exact[s % 16] += Fraction(float(rec["m"])) * Fraction(2) ** int(rec["e"])
+            adds[s % 16] += 1
+        o.merge_epoch()
+    assert int(o.gtours.sum()) == int(o.MG[0])
+    for k in range(16):
+        got = Fraction(float(o.gsum[k]["m"])) * Fraction(2) ** int(o.gsum[k]["e"])
+        assert exact[k] > 0
+        # one rounding per addition, each at most half an ulp (2^-53 relative)
+        assert abs(got / exact[k] - 1) <= (adds[k] + 5) * Fraction(1, 2 ** 53)
+    g = [float(exact[k] / int(o.gtours[k])) * 2.0 ** 0 for k in range(16)]
+    ref = statistics.stdev(g) / (4 * statistics.mean(g))
+    assert abs(o.error_estimate() / ref - 1) < 1e-12
+    # an empty group leaves the estimate undefined
+    assert oracle.Oracle(2, n_max, 8, 1, group_stats=True).error_estimate() == math.inf
