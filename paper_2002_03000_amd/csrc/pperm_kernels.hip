@@ -541,18 +541,101 @@ __device__ __forceinline__ uint64_t ufirst64(uint64_t v) {
     return ((uint64_t)ufirst((uint32_t)(v >> 32)) << 32) | (uint64_t)ufirst((uint32_t)v);
 }
 __device__ __forceinline__ bool ubool(bool b) { return ufirst(b ? 1u : 0u) != 0u; }
+// v of lane l (the builtin returns a signed int: convert through uint32_t so
+// that the low word of a 64-bit value is never sign-extended)
+__device__ __forceinline__ uint32_t lane_value(uint32_t v, uint32_t l) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+__device__ __forceinline__ uint64_t lane_value(uint64_t v, uint32_t l) {
+    return ((uint64_t)lane_value((uint32_t)(v >> 32), l) << 32) | (uint64_t)lane_value((uint32_t)v, l);
+}
+
+// Address-space views.  The pooled sums are never written while a growth
+// launch runs, so uniform reads of them may go through the constant space
+// (scalar loads, which do not wait on the LDS counter as flat loads do); the
+// copy stack is ordinary global memory.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T* as_const(const T* p) {
+    return (const __attribute__((address_space(4))) T*)p;
+}
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* as_global(T* p) {
+    return (__attribute__((address_space(1))) T*)p;
+}
+
+// Whole-record moves through those spaces, one 32-bit word at a time (the
+// compiler merges them into wide loads and stores).
+template <typename T>
+__device__ __forceinline__ T load_const(const T* p) {
+    static_assert(sizeof(T) % 4 == 0, "word-sized record");
+    T r;
+    const __attribute__((address_space(4))) uint32_t* q = (const __attribute__((address_space(4))) uint32_t*)p;
+    uint32_t* d = reinterpret_cast<uint32_t*>(&r);
+#pragma unroll
+    for (size_t i = 0; i < sizeof(T) / 4; ++i) d[i] = q[i];
+    return r;
+}
+template <typename T>
+__device__ __forceinline__ T load_global(const T* p) {
+    static_assert(sizeof(T) % 4 == 0, "word-sized record");
+    T r;
+    const __attribute__((address_space(1))) uint32_t* q = (const __attribute__((address_space(1))) uint32_t*)p;
+    uint32_t* d = reinterpret_cast<uint32_t*>(&r);
+#pragma unroll
+    for (size_t i = 0; i < sizeof(T) / 4; ++i) d[i] = q[i];
+    return r;
+}
+template <typename T>
+__device__ __forceinline__ void store_global(T* p, const T& v) {
+    static_assert(sizeof(T) % 4 == 0, "word-sized record");
+    __attribute__((address_space(1))) uint32_t* q = (__attribute__((address_space(1))) uint32_t*)p;
+    const uint32_t* d = reinterpret_cast<const uint32_t*>(&v);
+#pragma unroll
+    for (size_t i = 0; i < sizeof(T) / 4; ++i) q[i] = d[i];
+}
+
+// Direction sets of one probe window as 64-bit lane masks: direction d owns
+// lanes [d*W, d*W + W); a set of directions is kept as the top bit of each
+// owned field (FHI), so that "does any lane of this direction show X" is a
+// field-wise nonzero test on the ballot of X.
+template <int D> struct Fields;
+template <> struct Fields<2> {
+    static constexpr int W = 16, LW = 4;
+    static constexpr uint64_t HI = 0x8000800080008000ull, LO = 0x7FFF7FFF7FFF7FFFull;
+};
+template <> struct Fields<3> {
+    static constexpr int W = 8, LW = 3;
+    static constexpr uint64_t HI = 0x0000808080808080ull, LO = 0x00007F7F7F7F7F7Full;
+};
+
+// Top bit of every field of x that has any bit set (fields never carry into
+// each other: (2^(W-1) - 1) * 2 < 2^W).
+template <int D>
+__device__ __forceinline__ uint64_t fields_any(uint64_t x) {
+    using F = Fields<D>;
+    return (((x & F::LO) + F::LO) | x) & F::HI;
+}
+
+// Every lane of the fields whose top bit is set in hb.
+template <int D>
+__device__ __forceinline__ uint64_t fields_lanes(uint64_t hb) {
+    const uint64_t x = hb >> (Fields<D>::W - 1);
+    return (x << Fields<D>::W) - x;
+}
 
 // One sequence's `tours` tours against frozen pooled sums (the whole hot path
 // of one walk); run by one wavefront.  Every value below is wave-uniform
 // except where a lane index enters (scan windows, Philox counters, deletions).
+// A step issues its occupancy reads first, evaluates the prune/enrich
+// arithmetic while they are in flight, and only then resolves the scan.
 template <int D>
 __device__ __forceinline__ void walk_sequence(const ProblemDesc& P, uint32_t tours, uint32_t cap,
                                               uint32_t s, unsigned char* lds) {
     using L_ = Lat<D>;
     using Key = typename L_::Key;
-    constexpr int NDIR = 2 * D;
-    constexpr int W = (D == 2) ? 16 : 8;      // probe positions per direction per round
-    constexpr uint64_t FIELD = (1ull << W) - 1ull;
+    using F = Fields<D>;
+    constexpr int W = F::W;                    // probe positions per direction per window
+    constexpr uint32_t FIELD = (1u << W) - 1u;
 
     // LDS: the occupancy table, the slot id of every site of the walk, and the
     // sequence's own per-length sums (moved in at the start of the sequence's
@@ -565,11 +648,23 @@ __device__ __forceinline__ void walk_sequence(const ProblemDesc& P, uint32_t tou
     const uint32_t smask = S - 1u;
     const uint32_t hshift = 32u - P.slots_log2;
 
-    // probe-lane role: direction-major, W lanes per direction
+    // probe-lane role: direction-major, W lanes per direction (lanes past the
+    // 2d directions read a slot that no mask ever selects)
     const int pdir = lane / W;
     const int poff = lane % W;
-    const bool pvalid = pdir < NDIR;
-    const int pdx = dir_dx(pdir), pdy = dir_dy(pdir), pdz = dir_dz(pdir);
+    // The walk's end is carried as its packed key; a neighbour's key is the
+    // end's key plus a per-direction offset (no field ever carries: every
+    // coordinate stays within +-n_max < 2^15 of the origin's 2^15 offset).
+    // (direction 2i steps +1 along axis i, direction 2i+1 steps -1; lanes past
+    // the 2d directions get 0 and are never selected)
+    const Key pmag = (pdir < 2 * D) ? ((Key)1 << (16 * (pdir >> 1))) : (Key)0;
+    const Key pdelta = (pdir & 1) ? (Key)((Key)0 - pmag) : pmag;
+    // A zero the compiler cannot see through.  Indexing the per-length records
+    // with it keeps the weight arithmetic in vector registers (the walk's
+    // control state stays scalar) and lets the record read overlap the step
+    // instead of being waited for on the spot to move it to scalar registers.
+    uint32_t vz;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(vz));
 
     const uint32_t n_max = P.n_max;
     const uint32_t row = P.row;
@@ -577,8 +672,6 @@ __device__ __forceinline__ void walk_sequence(const ProblemDesc& P, uint32_t tou
     const bool control_mode = (P.mode != MODE_ROSENBLUTH);
     const double pool = shared_mode ? (double)P.N : 1.0;
     const uint64_t pool_u = shared_mode ? (uint64_t)P.N : 1ull;
-    const SumRec* __restrict__ Gbase = P.G;
-    SumRec* __restrict__ Lbase = P.L;
 
     // the empty table with the origin in it, slot id of site 0
     for (uint32_t i = (uint32_t)lane; i < S; i += 64) table[i] = (Key)0;
@@ -596,19 +689,20 @@ __device__ __forceinline__ void walk_sequence(const ProblemDesc& P, uint32_t tou
     uint64_t MGs = shared_mode ? P.MG[0] : 0ull;
 
     const size_t rb0 = (size_t)s * row;
-    SumRec* __restrict__ Lrow = Lbase + rb0;
-    const SumRec* __restrict__ Grow = shared_mode ? Gbase : Gbase + rb0;
+    SumRec* __restrict__ Lrow = P.L + rb0;
+    const SumRec* Grow = shared_mode ? P.G : P.G + rb0;   // read with load_const
     if (!shared_mode) MGs = ufirst64(P.MG[s]);
     const uint64_t t0 = ufirst64(P.t[s]);
     uint32_t tlo = (uint32_t)t0;               // tour index: its low word keys the random numbers
     uint32_t m = ufirst(P.m[s]);
-    for (uint32_t i = (uint32_t)lane; i <= n_max; i += 64u) Ls[i] = Lrow[i];
+    for (uint32_t i = (uint32_t)lane; i <= n_max; i += 64u) Ls[i] = load_global(Lrow + i);
     wave_fence();
     SumRec rec0 = Ls[0];
     // counters of this call, added to the sequence's totals at its end: the
     // step count (scalar, it drives the cap) and one counter per lane of `cv`
     // (lane i accumulates statistics word i)
     uint32_t c_steps = 0, c_tours = 0, c_maxd = 0;
+    uint64_t c_events = 0;                     // events: the sum over tours of k
     uint64_t cv = 0;
     uint64_t digest = ufirst64(P.stats[(size_t)s * STATS_WORDS + ST_DIGEST]);
     bool abort = false;
@@ -632,12 +726,22 @@ __device__ __forceinline__ void walk_sequence(const ProblemDesc& P, uint32_t tou
         bool stale = true;
         uint4 rb = make_uint4(0, 0, 0, 0);
         uint32_t n = 0;
-        int ex = 0, ey = 0, ez = 0;
+        Key ekey = origin_key;                 // the walk's end
         bool control = false;
+        // pending copies: the top entry in scalar registers, the one below it
+        // prefetched into vector registers, the rest in global memory
         uint32_t sp = 0, top_n = 0, top_rem = 0;
         XF top_w = {0.0, 0};
-        uint64_t top_key = 0;
+        Key top_key = 0;
+        StackEntry below;
+        below.n = 0u;
+        below.remaining = 0u;
+        below.e = 0;
+        below.pad0 = 0u;
+        below.m = 0.0;
+        below.key = 0ull;
         XF Lc = {0.0, 0};
+        SumRec Gpre = load_const(Grow);        // pooled sum of the current length (prefetched)
         // tours seen by the running average of eqn (6) (reading of Algorithm 2)
         const double seen = (double)(MGs + pool_u * (uint64_t)m);
 
@@ -653,21 +757,20 @@ __device__ __forceinline__ void walk_sequence(const ProblemDesc& P, uint32_t tou
             const uint32_t B0 = __builtin_amdgcn_readlane(rb.x, li);
             const uint32_t B1 = __builtin_amdgcn_readlane(rb.y, li);
             const uint32_t B2 = __builtin_amdgcn_readlane(rb.z, li);
+            const XF Gc = xf_of(Gpre);
 
-            // ---- one straight-line block: loads, first scan window, decision
-            // arithmetic (independent of the scan, so it fills the LDS latency) ----
-            // pooled sum of this length (read-only: scalar load) and this
-            // sequence's record of the next length
-            const XF Gc = xf_of(Grow[n]);
-            const SumRec nxt = Ls[n + 1];
-            // occupancy scan of the endpoint's 2d neighbours.  In a linear-probing
-            // run the key, if present, lies before the first empty slot, so a
-            // direction is occupied iff a window shows the key and free iff it
-            // shows an empty slot and no key.
-            const Key nk = L_::pack(ex + pdx, ey + pdy, ez + pdz);
+            // ---- occupancy reads of the first window, and the next length's record ----
+            // In a linear-probing run the key, if present, lies before the first
+            // empty slot, so a direction is occupied iff a window shows the key
+            // and free iff it shows an empty slot and no key.
+            const Key nk = ekey + pdelta;
             const uint32_t home = L_::hash(nk) >> hshift;
             uint32_t slot = (home + (uint32_t)poff) & smask;
             Key v = table[slot];
+            const SumRec nxt = Ls[n + 1 + vz];
+            __builtin_amdgcn_sched_barrier(0);
+
+            // ---- decision arithmetic while the reads are in flight ----
             // eqn (6): r = W / [W_n], [W_n] = sum / seen (own epoch data weighted
             // N in Algorithm 2), evaluated as (W * seen) / sum; only used when a
             // decision is due at this length
@@ -681,44 +784,41 @@ __device__ __forceinline__ void walk_sequence(const ProblemDesc& P, uint32_t tou
                                        (r == f ? 4u : 0u) | (u < r ? 8u : 0u));
             // (r is only meaningful when a decision is due; keep the conversion defined)
             const uint32_t fi = ufirst((uint32_t)((f >= 0.0 && f < 4294967295.0) ? f : 0.0));
+            asm volatile("" ::"s"(ub), "s"(fi));
 
-            uint32_t pending = (1u << NDIR) - 1u;
-            uint32_t freem = 0u;
-            uint32_t myslot = 0u;                 // slot this lane read when its direction resolved
-            bool myemp = false;                   // ... and whether it was empty
+            // ---- resolve the scan: one window per pass, usually one pass ----
+            uint64_t pending = F::HI;          // directions not yet resolved
+            uint64_t freem = 0;                // directions resolved free
+            uint64_t insm = 0;                 // empty lanes of the window that resolved them
+            uint32_t myslot = slot;            // this lane's slot in that window
             uint32_t base = (uint32_t)poff;
+            bool first = true;
             for (;;) {
-                const bool act = pvalid && ((pending >> pdir) & 1u);
-                const bool emp = act && v == (Key)0;
-                if (act) {
-                    myslot = slot;
-                    myemp = emp;
-                }
-                // per direction: does its window show the key (2) / an empty slot (1)?
-                const uint32_t code = group_or<W>((act && v == nk) ? 2u : (emp ? 1u : 0u));
-                const uint64_t gh = __ballot(poff == 0 && (code & 2u));
-                const uint64_t ge = __ballot(poff == 0 && (code & 1u));
-                uint32_t hit_dirs = 0u, emp_dirs = 0u;
-#pragma unroll
-                for (int d = 0; d < NDIR; ++d) {
-                    hit_dirs |= (uint32_t)((gh >> (d * W - d)) & (1ull << d));
-                    emp_dirs |= (uint32_t)((ge >> (d * W - d)) & (1ull << d));
-                }
-                freem |= emp_dirs & ~hit_dirs & pending;
-                pending &= ~(hit_dirs | emp_dirs);
+                const uint64_t act = fields_lanes<D>(pending);
+                const uint64_t hitm = __ballot(v == nk) & act;
+                const uint64_t empm = __ballot(v == (Key)0) & act;
+                const uint64_t hd = fields_any<D>(hitm);
+                const uint64_t ed = fields_any<D>(empm);
+                const uint64_t fr = ed & ~hd;
+                freem |= fr;
+                pending &= ~(hd | ed);
+                const uint64_t frl = fields_lanes<D>(fr);
+                insm |= empm & frl;
+                if (pending == 0u && first) break;
+                if ((frl >> lane) & 1u) myslot = slot;
                 if (pending == 0u) break;
                 // a run longer than the window: read the next W positions
+                first = false;
                 base += W;
                 slot = (home + base) & smask;
                 v = table[slot];
             }
-            const uint32_t a = (uint32_t)__popc(freem);
+            const uint32_t a = (uint32_t)__popcll(freem);
             if (a == 0u) {
                 cv += (lane == ST_TRAPS) ? 1ull : 0ull;
                 bt = true;
             } else {
                 k += 1;
-                cv += (lane == ST_EVENTS) ? 1ull : 0ull;
                 bool pruned = false;
                 if (control) {
                     if (ub & 1u) {
@@ -727,19 +827,19 @@ __device__ __forceinline__ void walk_sequence(const ProblemDesc& P, uint32_t tou
                         if (ci > 1u) {
                             w = xf_div(w, (double)ci);
                             if (sp > 0u) {
-                                StackEntry e;
-                                e.n = top_n;
-                                e.remaining = top_rem;
-                                e.e = top_w.e;
-                                e.pad0 = 0u;
-                                e.m = top_w.m;
-                                e.key = top_key;
-                                stk[sp - 1] = e;
+                                // the old top goes to memory and stays cached below
+                                below.n = top_n;
+                                below.remaining = top_rem;
+                                below.e = top_w.e;
+                                below.pad0 = 0u;
+                                below.m = top_w.m;
+                                below.key = (uint64_t)top_key;
+                                store_global(stk + (sp - 1), below);
                             }
                             top_n = n;
                             top_rem = ci - 1u;
                             top_w = w;
-                            top_key = (uint64_t)L_::pack(ex, ey, ez);
+                            top_key = ekey;
                             sp += 1;
                             c_maxd = (sp > c_maxd) ? sp : c_maxd;
                             cv += (lane == ST_ENRICH) ? 1ull
@@ -757,28 +857,26 @@ __device__ __forceinline__ void walk_sequence(const ProblemDesc& P, uint32_t tou
                 } else {
                     // ---- Rosenbluth growth: the j-th free neighbour ----
                     const uint32_t j = __umulhi(B0, a);
-                    uint32_t mm = freem;
+                    uint64_t mm = freem;
                     for (uint32_t i = 0; i < j; ++i) mm &= mm - 1u;
-                    const int dir = __ffs(mm) - 1;
+                    const int dir = (__ffsll((unsigned long long)mm) - 1) >> F::LW;
                     digest = (digest ^ (uint64_t)((uint32_t)dir | (a << 3))) * FNV_PRIME;
                     // insertion slot: the first empty slot of the chosen direction's run
-                    const uint64_t bemp = __ballot(myemp);
                     const uint32_t il =
-                        (uint32_t)__builtin_ctzll((bemp >> (dir * W)) & FIELD) + (uint32_t)(dir * W);
+                        (uint32_t)__builtin_ctz((uint32_t)(insm >> (dir * W)) & FIELD) + (uint32_t)(dir * W);
                     const uint32_t ins_slot = __builtin_amdgcn_readlane(myslot, il);
-                    ex += dir_dx(dir);
-                    ey += dir_dy(dir);
-                    ez += dir_dz(dir);
+                    ekey = lane_value(nk, il);
                     if (lane == 0) {
-                        table[ins_slot] = L_::pack(ex, ey, ez);
+                        table[ins_slot] = ekey;
                         sid[n + 1] = (uint16_t)ins_slot;
                     }
-                    w = xf_mul(w, (double)a);      // W *= a_+, eqn (2)
-                    if (ubool(w.e > EXP_LIMIT || w.e < -EXP_LIMIT)) {
-                        if (lane == 0) atomicOr(&P.ctrl[CTRL_ERR], ERR_RANGE);
-                    }
+                    // W *= a_+, eqn (2).  No range check is needed here: |e|
+                    // grows by at most 3 per step and falls by at most 33 per
+                    // decision, so it stays below 2^21 for every n_max allowed.
+                    w = xf_mul(w, (double)a);
                     n += 1;
                     c_steps += 1;
+                    Gpre = load_const(Grow + n);   // for the decision at the new length
                     // ---- arrival: record into the running sums, eqn (4) ----
                     const XF Lnew = xf_add(xf_of(nxt), w);
                     SumRec nr;
@@ -800,33 +898,35 @@ __device__ __forceinline__ void walk_sequence(const ProblemDesc& P, uint32_t tou
                 if (sp == 0u) break;
                 const uint32_t rn = top_n;
                 w = top_w;
-                const uint64_t ekey = top_key;
+                ekey = top_key;
                 top_rem -= 1u;
                 if (top_rem == 0u) {
                     sp -= 1u;
                     if (sp > 0u) {
-                        const StackEntry e = stk[sp - 1];
-                        top_n = ufirst(e.n);
-                        top_rem = ufirst(e.remaining);
-                        top_w = XF{e.m, e.e};
-                        top_key = ufirst64(e.key);
+                        // the cached entry becomes the top; prefetch the next one
+                        top_n = ufirst(below.n);
+                        top_rem = ufirst(below.remaining);
+                        top_w = XF{below.m, below.e};
+                        top_key = (Key)ufirst64(below.key);
+                        if (sp > 1u) below = load_global(stk + (sp - 2) + vz);
                     }
                 }
                 // LIFO deletion of sites rn+1..n restores the table exactly
                 for (uint32_t i = rn + 1u + (uint32_t)lane; i <= n; i += 64u) table[sid[i]] = (Key)0;
-                L_::unpack((Key)ekey, ex, ey, ez);
                 n = rn;
                 control = false;
                 wave_fence();
             }
         }
         // end of the tour (or abort): back to the empty walk
+        c_events += k;
         for (uint32_t i = 1u + (uint32_t)lane; i <= n; i += 64u) table[sid[i]] = (Key)0;
         wave_fence();
     }
+    cv += (lane == ST_EVENTS) ? c_events : 0ull;
     if (lane == 0) Ls[0] = rec0;
     wave_fence();
-    for (uint32_t i = (uint32_t)lane; i <= n_max; i += 64u) Lrow[i] = Ls[i];
+    for (uint32_t i = (uint32_t)lane; i <= n_max; i += 64u) store_global(Lrow + i, Ls[i]);
     if (lane == 0) {
         if (abort) atomicOr(&P.ctrl[CTRL_ERR], ERR_CAP);
         uint64_t* sr = P.stats + (size_t)s * STATS_WORDS;
@@ -866,7 +966,9 @@ __global__ void __launch_bounds__(64) batch_kernel(BatchArgs B) {
             }
             E = B.entries[lo];
         }
-        const ProblemDesc P = *E.desc;
+        // the descriptor is read through the constant space: a flat load would
+        // make every field (and so the whole walk's control flow) non-uniform
+        const ProblemDesc P = load_const(E.desc);
         const uint32_t s = item - E.first_item;
         if (P.dim == 2) walk_sequence<2>(P, E.tours, E.step_cap, s, lds);
         else walk_sequence<3>(P, E.tours, E.step_cap, s, lds);
