@@ -98,7 +98,8 @@ int resolve_shape(const pperm_config* c, Shape* sh) {
     sh->walks_per_wave = wpw;
     sh->team_lanes = 64u / wpw;
     // the wave-per-walk kernel also keeps the sequence's sums in LDS
-    sh->lds_wg_bytes = (wpw == 1) ? sh->lds_team_bytes + (uint32_t)align_up(c->n_max + 1u, 16) * 16u
+    sh->lds_wg_bytes = (wpw == 1) ? sh->lds_team_bytes + (uint32_t)align_up(c->n_max + 1u, 16) * 16u +
+                                        LDS_STACK * (uint32_t)sizeof(StackEntry)
                                   : sh->lds_team_bytes * wpw;
     if (sh->lds_wg_bytes > (wpw == 1 ? kLdsLimit : kTeamLdsLimit)) return PPERM_EINVAL;
     return PPERM_OK;
@@ -453,7 +454,8 @@ int pperm_run_batch(pperm_ctx* const* ctxs, size_t count, const uint32_t* tours_
         const uint64_t pooled = (x->cfg.mode == PPERM_SHARED) ? x->merged_tours + N * per_seq_total
                                                               : x->merged_tours + per_seq_total;
         if (pooled > 0xFFFFFFFFull || per_seq_total > 0xFFFFFFFFull) return PPERM_EOVERFLOW;
-        const uint32_t lds = x->desc.lds_team_bytes + x->desc.row * (uint32_t)sizeof(SumRec);
+        const uint32_t lds = x->desc.lds_team_bytes + x->desc.row * (uint32_t)sizeof(SumRec) +
+                             LDS_STACK * (uint32_t)sizeof(StackEntry);
         items.push_back({x, tours_each[i], lds,
                          (double)N * tours_each[i] * (double)(x->cfg.n_max + 1)});
     }

@@ -19,7 +19,10 @@ enum : uint32_t { CTRL_QUEUE = 0, CTRL_ERR = 1, CTRL_WORDS = 16 };
 enum : uint32_t { MODE_SHARED = 0, MODE_INDEPENDENT = 1, MODE_ROSENBLUTH = 2 };
 
 constexpr int STATS_WORDS = 10;
-constexpr uint32_t GROUPS = 16;   // sequence groups of the error estimate (s mod 16)
+constexpr uint32_t GROUPS = 16;
+// Copy-stack entries kept in LDS per wave-per-walk sequence (positions
+// 0 .. LDS_STACK-1 from the bottom; deeper ones live in global memory).
+constexpr uint32_t LDS_STACK = 32;   // sequence groups of the error estimate (s mod 16)
 enum : int { ST_STEPS = 0, ST_EVENTS, ST_ENRICH, ST_COPIES, ST_PRUNES, ST_TRAPS,
              ST_TOURS, ST_MAXDEPTH, ST_DIGEST, ST_CAPPED };
 

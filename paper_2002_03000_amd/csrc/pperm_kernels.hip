@@ -637,12 +637,13 @@ __device__ __forceinline__ void walk_sequence(const ProblemDesc& P, uint32_t tou
     constexpr int W = F::W;                    // probe positions per direction per window
     constexpr uint32_t FIELD = (1u << W) - 1u;
 
-    // LDS: the occupancy table, the slot id of every site of the walk, and the
+    // LDS: the occupancy table, the slot id of every site of the walk, the
     // sequence's own per-length sums (moved in at the start of the sequence's
-    // tours and back out at their end)
+    // tours and back out at their end) and the bottom of its copy stack
     Key* table = reinterpret_cast<Key*>(lds);
     uint16_t* sid = reinterpret_cast<uint16_t*>(lds + (sizeof(Key) << P.slots_log2));
     SumRec* Ls = reinterpret_cast<SumRec*>(lds + P.lds_team_bytes);
+    StackEntry* lstk = reinterpret_cast<StackEntry*>(lds + P.lds_team_bytes + P.row * sizeof(SumRec));
     const int lane = (int)threadIdx.x;
     const uint32_t S = 1u << P.slots_log2;
     const uint32_t smask = S - 1u;
@@ -728,20 +729,13 @@ __device__ __forceinline__ void walk_sequence(const ProblemDesc& P, uint32_t tou
         uint32_t n = 0;
         Key ekey = origin_key;                 // the walk's end
         bool control = false;
-        // pending copies: the top entry in scalar registers, the one below it
-        // prefetched into vector registers, the rest in global memory
+        // pending copies: the top entry in scalar registers, the others at
+        // positions 0 .. sp-2 (LDS below LDS_STACK, global memory above)
         uint32_t sp = 0, top_n = 0, top_rem = 0;
         XF top_w = {0.0, 0};
         Key top_key = 0;
-        StackEntry below;
-        below.n = 0u;
-        below.remaining = 0u;
-        below.e = 0;
-        below.pad0 = 0u;
-        below.m = 0.0;
-        below.key = 0ull;
         XF Lc = {0.0, 0};
-        SumRec Gpre = load_const(Grow);        // pooled sum of the current length (prefetched)
+        SumRec Gpre = load_const(Grow);        // pooled sum of the current length
         // tours seen by the running average of eqn (6) (reading of Algorithm 2)
         const double seen = (double)(MGs + pool_u * (uint64_t)m);
 
@@ -757,7 +751,11 @@ __device__ __forceinline__ void walk_sequence(const ProblemDesc& P, uint32_t tou
             const uint32_t B0 = __builtin_amdgcn_readlane(rb.x, li);
             const uint32_t B1 = __builtin_amdgcn_readlane(rb.y, li);
             const uint32_t B2 = __builtin_amdgcn_readlane(rb.z, li);
+            // pooled sums: this length's (loaded a step ago) and the next one's,
+            // which the following step uses if this one grows the walk (a step
+            // never starts at n_max, so n + 1 is inside the row)
             const XF Gc = xf_of(Gpre);
+            const SumRec Gnx = load_const(Grow + (n + 1u));
 
             // ---- occupancy reads of the first window, and the next length's record ----
             // In a linear-probing run the key, if present, lies before the first
@@ -827,14 +825,19 @@ __device__ __forceinline__ void walk_sequence(const ProblemDesc& P, uint32_t tou
                         if (ci > 1u) {
                             w = xf_div(w, (double)ci);
                             if (sp > 0u) {
-                                // the old top goes to memory and stays cached below
-                                below.n = top_n;
-                                below.remaining = top_rem;
-                                below.e = top_w.e;
-                                below.pad0 = 0u;
-                                below.m = top_w.m;
-                                below.key = (uint64_t)top_key;
-                                store_global(stk + (sp - 1), below);
+                                // the old top goes to position sp - 1
+                                StackEntry e;
+                                e.n = top_n;
+                                e.remaining = top_rem;
+                                e.e = top_w.e;
+                                e.pad0 = 0u;
+                                e.m = top_w.m;
+                                e.key = (uint64_t)top_key;
+                                if (sp - 1u < LDS_STACK) {
+                                    if (lane == 0) lstk[sp - 1u] = e;
+                                } else {
+                                    store_global(stk + (sp - 1u), e);
+                                }
                             }
                             top_n = n;
                             top_rem = ci - 1u;
@@ -876,7 +879,7 @@ __device__ __forceinline__ void walk_sequence(const ProblemDesc& P, uint32_t tou
                     w = xf_mul(w, (double)a);
                     n += 1;
                     c_steps += 1;
-                    Gpre = load_const(Grow + n);   // for the decision at the new length
+                    Gpre = Gnx;
                     // ---- arrival: record into the running sums, eqn (4) ----
                     const XF Lnew = xf_add(xf_of(nxt), w);
                     SumRec nr;
@@ -903,12 +906,12 @@ __device__ __forceinline__ void walk_sequence(const ProblemDesc& P, uint32_t tou
                 if (top_rem == 0u) {
                     sp -= 1u;
                     if (sp > 0u) {
-                        // the cached entry becomes the top; prefetch the next one
-                        top_n = ufirst(below.n);
-                        top_rem = ufirst(below.remaining);
-                        top_w = XF{below.m, below.e};
-                        top_key = (Key)ufirst64(below.key);
-                        if (sp > 1u) below = load_global(stk + (sp - 2) + vz);
+                        const StackEntry e = (sp - 1u < LDS_STACK) ? lstk[sp - 1u]
+                                                                    : load_global(stk + (sp - 1u));
+                        top_n = ufirst(e.n);
+                        top_rem = ufirst(e.remaining);
+                        top_w = XF{e.m, e.e};
+                        top_key = (Key)ufirst64(e.key);
                     }
                 }
                 // LIFO deletion of sites rn+1..n restores the table exactly
