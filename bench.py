@@ -32,6 +32,37 @@ ALG_OPS_PER_STEP = {2: 100 + 7 * 3 + 15 + 15 + 6, 3: 100 + 7 * 5 + 15 + 15 + 6}
 # MI355X 32-bit VALU peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one lane-op per lane per clock).
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
+PROFILES = os.path.join(ROOT, "profiles")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2002_03000_amd", "csrc", "pperm_kernels.hip")
+
+
+def measured_traffic(name):
+    """HBM bytes per launch of the growth kernel from a committed counter
+    summary, or None when the kernel source has changed since it was taken."""
+    path = os.path.join(PROFILES, name)
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("|", "#", " ")):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    if fields.get("kernel_code_sha256") != kernel_code_digest() or "traffic_bytes_per_launch" not in fields:
+        return None
+    return int(fields["traffic_bytes_per_launch"])
+
+
+def kernel_code_digest():
+    """sha256 of the kernel source with comments and blank lines removed: the
+    key under which counter summaries stay valid."""
+    import hashlib
+    import re
+    src = open(KERNEL_SOURCE).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    lines = [re.sub(r"//.*$", "", ln).rstrip() for ln in src.splitlines()]
+    return hashlib.sha256("\n".join(ln for ln in lines if ln.strip()).encode()).hexdigest()
+
+
 WORKLOADS = {
     "parallel2d": workloads.PARALLEL_2D,
     "parallel3d": workloads.PARALLEL_3D,
@@ -86,7 +117,18 @@ def main():
     ap.add_argument("--serve-pool-gib", type=float, default=8.0)
     ap.add_argument("--serve-max-sequences", type=int, default=32768)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-digest", action="store_true",
+                    help="print the digest that keys the committed counter summaries")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (to calibrate the HBM byte counters)")
     args = ap.parse_args()
+
+    if args.kernel_digest:
+        print(kernel_code_digest())
+        return
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding "
@@ -181,14 +223,29 @@ def main():
                    "launch": shape},
         "cn_rel_err_nmax": rel_err,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
-                     "frac": achieved / ALU_PEAK_TOPS, "traffic": None,
-                     "kernel": "run_kernel", "avg_launch_ms": run_ms / launches,
+                     "frac": achieved / ALU_PEAK_TOPS,
+                     "traffic": measured_traffic(f"batch_kernel_{args.workload}_traffic.md")
+                     if not args.epochs else None,
+                     "kernel": "batch_kernel", "avg_launch_ms": run_ms / launches,
                      "alg_ops_per_step": ops},
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(p)
     print(json.dumps(line), flush=True)
+
+
+def copy_calibration(nbytes=1 << 30):
+    """A plain device copy of a known size: under `rocprofv3 --pmc FETCH_SIZE`
+    (then WRITE_SIZE) the copy reads and writes exactly nbytes, so counter /
+    nbytes converts another kernel's counter into bytes."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes}), flush=True)
 
 
 def _log(msg):

@@ -4,24 +4,22 @@
 // eqn (6)), accumulation of the sample sums (eqn (4)), and the merge of the
 // per-sequence sums into the pooled sums of Algorithm 2 (Sec. 3, Fig. 1).
 //
-// Execution model.  A "team" of TS lanes of one 64-lane wavefront owns one
-// walk, i.e. one flatPERM sequence at a time; 64/TS walks share a wave.  Every
-// lane of a team holds the team's walk state (so every lane can take every
-// decision and no broadcast is needed), and the lanes split the parallel parts
-// of a step between them:
+// Execution model.  The default growth kernel (batch_kernel) is persistent:
+// one 64-lane wavefront takes one (problem, sequence) item at a time from a
+// device queue and runs that sequence's tours; every walk quantity is uniform
+// over the wave, and the lanes split the parallel parts of a step:
 //   - the occupancy scan: lane (dir, off) reads slot home(dir)+off+W*round of
 //     the walk's open-addressing table, so the 2d neighbours and W consecutive
 //     probe positions per neighbour are looked up in one LDS instruction and
-//     resolved with wave ballots;
-//   - the random numbers: lane i of a team computes the Philox4x32-10 block
-//     of event k0+i, so one pass of the (quarter-rate) multiplies serves TS
-//     events; a step fetches its block with one lane shuffle per word;
+//     resolved with two wave ballots;
+//   - the random numbers: lane i computes the Philox4x32-10 block of event
+//     k0+i, so one pass of the (quarter-rate) multiplies serves 64 events;
 //   - the LIFO deletion of abandoned sites after a backtrack.
 // The walk's occupancy table (packed int16 coordinates, linear probing,
-// restored exactly by LIFO deletion through remembered slot ids) and the
-// slot-id array live in LDS.  The pending-copy stack lives in global memory
-// with its top entry in registers.  Sequence sums L, H live in global memory
-// (L2-resident); the values for the next length are prefetched one step ahead.
+// restored exactly by LIFO deletion through remembered slot ids), the slot
+// ids, the sequence's own per-length sums and the bottom of its copy stack
+// live in LDS; the pooled sums are read with scalar loads.  A second kernel
+// (run_kernel) packs 64/TS walks into a wave as teams of TS lanes.
 //
 // Determinism.  Every floating-point decision uses the same IEEE operations
 // in the same order as the reading of the method these kernels implement
