@@ -110,6 +110,8 @@ def main():
     ap.add_argument("--walks-per-wave", type=int, default=0)
     ap.add_argument("--hash-slots", type=int, default=0)
     ap.add_argument("--problems", type=int, default=0, help="batched: use the first P problems of the mix")
+    ap.add_argument("--lockstep", action="store_true",
+                    help="batched: lock-step rounds of batched calls instead of device-chained epochs")
     ap.add_argument("--serve-duration", type=float, default=60.0, help="served: arrival window (s)")
     ap.add_argument("--serve-rate", type=float, default=50.0, help="served: arrivals per second")
     ap.add_argument("--serve-cap", type=int, default=4096, help="served: tour cap per job")
@@ -273,13 +275,17 @@ def run_batched(args, plain_budget_s=40.0):
         return ParallelFlatPERM(p.dim, p.n_max, p.n_sequences, p.seed + offset, mode=p.mode,
                                 stream_id=p.stream)
 
+    from paper_2002_03000_amd import run_job
     batch = Batch(len(mix))
     # warm-up: the first two epochs of a few problems, their own seeds
     warm = [make(p, 7_000_000) for p in mix[:8]]
-    for r in range(2):
-        batch.run_tours(warm, [s[r] for s in scheds[:8]])
-        for g in warm:
-            g.merge_epoch()
+    if args.lockstep:
+        for r in range(2):
+            batch.run_tours(warm, [s[r] for s in scheds[:8]])
+            for g in warm:
+                g.merge_epoch()
+    else:
+        run_job(warm, [s[:2] for s in scheds[:8]], stream=stream)
     torch.cuda.synchronize()
     for g in warm:
         g.close()
@@ -291,21 +297,37 @@ def run_batched(args, plain_budget_s=40.0):
         probs = [make(p, k) for p in mix]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        last = t0
-        for r in range(rounds):
-            tours = [s[r] if r < len(s) else 0 for s in scheds]
+        if args.lockstep:
+            # every problem's epoch of a round in one batched call, then the merges
+            last = t0
+            for r in range(rounds):
+                tours = [s[r] if r < len(s) else 0 for s in scheds]
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                batch.run_tours(probs, tours)
+                b.record(stream)
+                events.append((a, b))
+                for g, t in zip(probs, tours):
+                    if t:
+                        g.merge_epoch()
+                torch.cuda.synchronize()
+                if time.perf_counter() - last > 10:
+                    last = time.perf_counter()
+                    _log(f"batched job {k}: round {r + 1}/{rounds}, {last - t0:.1f} s")
+        else:
+            # the whole job in persistent launches that chain epochs on the device
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             a.record(stream)
-            batch.run_tours(probs, tours)
+            ws = run_job(probs, scheds, stream=stream)
             b.record(stream)
             events.append((a, b))
-            for g, t in zip(probs, tours):
-                if t:
-                    g.merge_epoch()
-            torch.cuda.synchronize()
-            if time.perf_counter() - last > 10:
-                last = time.perf_counter()
-                _log(f"batched job {k}: round {r + 1}/{rounds}, {last - t0:.1f} s")
+            last = t0
+            while not b.query():
+                time.sleep(0.5)
+                if time.perf_counter() - last > 10:
+                    last = time.perf_counter()
+                    _log(f"batched job {k}: running, {last - t0:.0f} s")
+            del ws
         ests = [g.estimates() for g in probs]
         torch.cuda.synchronize()
         elapsed_total += time.perf_counter() - t0
@@ -361,15 +383,17 @@ def run_batched(args, plain_budget_s=40.0):
         "data": "synthetic (walks grown from parameters; seeds per problem)",
         "config": {"workload": f"batched mix of {len(mix)} independent problems (seed 4): d in {{2,3}}, "
                                f"n_max in [64,2048], N in 64..1024, {total_tours} tours in total, "
-                               f"{rounds} batched rounds",
-                   "problems": len(mix), "rounds": rounds,
+                               + (f"{rounds} lock-step batched rounds" if args.lockstep else
+                                  "epochs chained on the device in one persistent launch per LDS class"),
+                   "problems": len(mix), "rounds": rounds, "lockstep": bool(args.lockstep),
                    "walk_steps_per_job": steps_total // args.steps},
         "plain_path": {"value": plain_steps / plain_dt, "unit": "walk-steps/s",
                        "sample": f"the first {plain_problems} problems of the mix one at a time "
                                  f"({plain_epochs} epochs, {plain_steps} walk-steps) in {plain_dt:.2f} s"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
                      "frac": achieved / ALU_PEAK_TOPS, "traffic": None,
-                     "kernel": "batch_kernel", "avg_launch_ms": run_ms / len(events),
+                     "kernel": "batch_kernel" if args.lockstep else "job_kernel",
+                     "avg_launch_ms": run_ms / len(events),
                      "alg_ops_per_step": ops},
         "cpu_baseline": None,
     }

@@ -157,6 +157,27 @@ int pperm_batch_workspace_bytes(size_t count, size_t* bytes);
 int pperm_run_batch(pperm_ctx* const* ctxs, size_t count, const uint32_t* tours_each,
                     void* d_workspace, size_t bytes, void* hip_stream);
 
+/* Device bytes of the scratch pperm_run_job needs for these contexts and
+ * epoch counts. */
+int pperm_job_workspace_bytes(pperm_ctx* const* ctxs, const uint32_t* epochs, size_t count,
+                              size_t* bytes);
+
+/* Whole epoch schedules in persistent launches: context ctxs[i] runs epochs[i]
+ * epochs, epoch e being schedules[i][e] tours per sequence followed by the
+ * merge, exactly as the calls pperm_run_tours(schedules[i][e]) and
+ * pperm_merge_epoch would (Algorithm 2, Sec. 3; same bits).  Each problem
+ * moves to its next epoch as soon as its own merge is done: sequences merge
+ * into the aligned pairwise tree as they finish, on the device.  Problems run
+ * in up to four LDS classes, one persistent launch each on library streams
+ * forked from and joined into hip_stream (NULL: the default stream), which
+ * must be ordered after all earlier work of the contexts.  d_workspace:
+ * caller-owned device memory of pperm_job_workspace_bytes, 256-byte aligned.
+ * Errors: EINVAL (bad arguments, a zero entry in a schedule, a context twice,
+ * another device, PPERM_INDEPENDENT mode, several walks per wave), ESTATE (a
+ * context with unmerged tours), EOVERFLOW, EDEVICE. */
+int pperm_run_job(pperm_ctx* const* ctxs, const uint32_t* const* schedules, const uint32_t* epochs,
+                  size_t count, void* d_workspace, size_t bytes, void* hip_stream);
+
 /* Synchronise the stream and read the merged state into caller-owned host
  * buffers of `len` >= n_max + 1 entries:
  *   log_cn[n] = log of the estimate of c_n (eqn (4); the mean of eqn (7) in

@@ -248,6 +248,7 @@ int pperm_create(const pperm_config* cfg, void* d_workspace, size_t bytes, void*
     d.L = at<SumRec>(x, L.L);
     d.G = at<SumRec>(x, L.G);
     d.MG = at<uint64_t>(x, L.MG);
+    d.HG = at<uint64_t>(x, L.HG);
     d.m = at<uint32_t>(x, L.m);
     d.t = at<uint64_t>(x, L.t);
     d.stats = at<uint64_t>(x, L.stats);
@@ -542,6 +543,229 @@ int pperm_run_batch(pperm_ctx* const* ctxs, size_t count, const uint32_t* tours_
     }
     for (size_t c = 0; c < classes.size(); ++c) HIP_TRY(hipStreamWaitEvent(stream, ds->join[c], 0));
     for (const BatchItem& it : items) it.ctx->open_tours += it.tours;
+    return PPERM_OK;
+}
+
+// ---- device-side epoch chaining ----------------------------------------------
+namespace {
+
+uint32_t lds_of(const pperm_ctx* x) {
+    return x->desc.lds_team_bytes + x->desc.row * (uint32_t)sizeof(SumRec) +
+           LDS_STACK * (uint32_t)sizeof(StackEntry);
+}
+
+uint32_t pow2_at_least(uint32_t n) {
+    uint32_t p = 1;
+    while (p < n) p <<= 1;
+    return p;
+}
+
+// Workspace of a job: the common part, then per problem its schedule, the
+// per-epoch copies of its pooled sums and its merge-tree flags.
+struct JobLayout {
+    uint64_t probs, state, order, counters, total;
+    std::vector<uint64_t> sched, gver, flags;
+};
+
+void job_layout(pperm_ctx* const* ctxs, const uint32_t* epochs, size_t count, JobLayout* L) {
+    uint64_t off = 0;
+    auto take = [&](uint64_t bytes) {
+        const uint64_t o = off;
+        off = align_up(off + (bytes ? bytes : 1), 256);
+        return o;
+    };
+    L->probs = take(count * sizeof(JobProblem));
+    L->state = take(count * sizeof(JobState));
+    L->order = take(count * 4);
+    L->counters = take(JOB_COUNTER_WORDS * 4);
+    L->sched.assign(count, 0);
+    L->gver.assign(count, 0);
+    L->flags.assign(count, 0);
+    for (size_t i = 0; i < count; ++i) {
+        const pperm_ctx* x = ctxs[i];
+        L->sched[i] = take((uint64_t)epochs[i] * 4);
+        L->gver[i] = take((uint64_t)epochs[i] * (x->lay.row + JOB_GAP) * sizeof(SumRec));
+        L->flags[i] = take((uint64_t)pow2_at_least(x->cfg.n_sequences) * 4);
+    }
+    L->total = off;
+}
+
+int job_validate(pperm_ctx* const* ctxs, const uint32_t* const* schedules, const uint32_t* epochs,
+                 size_t count, int* device_out) {
+    if (!ctxs || !epochs || count == 0) return PPERM_EINVAL;
+    int device = -1;
+    HIP_TRY(hipGetDevice(&device));
+    for (size_t i = 0; i < count; ++i) {
+        pperm_ctx* x = ctxs[i];
+        if (!x || x->device != device || x->team_lanes != 64) return PPERM_EINVAL;
+        if (x->cfg.mode == PPERM_INDEPENDENT) return PPERM_EINVAL;
+        for (size_t j = 0; j < i; ++j)
+            if (ctxs[j] == x) return PPERM_EINVAL;
+        if (x->open_tours != 0) return PPERM_ESTATE;
+        if (schedules) {
+            if (epochs[i] && !schedules[i]) return PPERM_EINVAL;
+            uint64_t total = 0;
+            for (uint32_t e = 0; e < epochs[i]; ++e) {
+                if (schedules[i][e] == 0) return PPERM_EINVAL;
+                total += schedules[i][e];
+            }
+            if (x->merged_tours + (uint64_t)x->cfg.n_sequences * total > 0xFFFFFFFFull) return PPERM_EOVERFLOW;
+        }
+    }
+    if (device_out) *device_out = device;
+    return PPERM_OK;
+}
+
+}  // namespace
+
+int pperm_job_workspace_bytes(pperm_ctx* const* ctxs, const uint32_t* epochs, size_t count, size_t* bytes) {
+    if (!bytes) return PPERM_EINVAL;
+    int rc = job_validate(ctxs, nullptr, epochs, count, nullptr);
+    if (rc) return rc;
+    JobLayout L;
+    job_layout(ctxs, epochs, count, &L);
+    *bytes = (size_t)L.total;
+    return PPERM_OK;
+}
+
+int pperm_run_job(pperm_ctx* const* ctxs, const uint32_t* const* schedules, const uint32_t* epochs,
+                  size_t count, void* d_workspace, size_t bytes, void* hip_stream) {
+    if (!schedules || !d_workspace) return PPERM_EINVAL;
+    int device = -1;
+    int rc = job_validate(ctxs, schedules, epochs, count, &device);
+    if (rc) return rc;
+    JobLayout L;
+    job_layout(ctxs, epochs, count, &L);
+    if (bytes < L.total || ((uintptr_t)d_workspace & 255u)) return PPERM_EINVAL;
+    hipStream_t stream = (hipStream_t)hip_stream;
+    unsigned char* ws = (unsigned char*)d_workspace;
+
+    // LDS classes (powers of two from 8 KB, at most four: the smallest fold
+    // upwards), then the order in which waves look for work: classes from
+    // the largest, inside a class the longest chain of steps first
+    std::vector<uint32_t> cls_lds;
+    std::vector<uint32_t> pcls(count, 0);
+    {
+        std::vector<uint32_t> sizes;
+        for (size_t i = 0; i < count; ++i) {
+            if (!epochs[i]) continue;
+            uint32_t c = 8192;
+            while (c < lds_of(ctxs[i])) c <<= 1;
+            sizes.push_back(c);
+        }
+        std::sort(sizes.begin(), sizes.end());
+        sizes.erase(std::unique(sizes.begin(), sizes.end()), sizes.end());
+        while (sizes.size() > (size_t)kBatchStreams) sizes.erase(sizes.begin());
+        cls_lds = sizes;
+        for (size_t i = 0; i < count; ++i) {
+            if (!epochs[i]) continue;
+            const uint32_t need = lds_of(ctxs[i]);
+            uint32_t c = 0;
+            while (cls_lds[c] < need) ++c;
+            pcls[i] = c;
+        }
+    }
+    if (cls_lds.empty()) return PPERM_OK;               // no epochs at all
+    const uint32_t K = (uint32_t)cls_lds.size();
+    std::vector<double> chain(count, 0.0), work(K, 0.0);
+    std::vector<uint32_t> in_cls(K, 0), seqs_upto(K, 0);
+    std::vector<uint32_t> order;
+    for (size_t i = 0; i < count; ++i) {
+        if (!epochs[i]) continue;
+        double t = 0;
+        for (uint32_t e = 0; e < epochs[i]; ++e) t += schedules[i][e];
+        chain[i] = t * (ctxs[i]->cfg.n_max + 1.0);
+        work[pcls[i]] += chain[i] * ctxs[i]->cfg.n_sequences;
+        in_cls[pcls[i]] += 1;
+        order.push_back((uint32_t)i);
+    }
+    std::sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+        if (pcls[a] != pcls[b]) return pcls[a] > pcls[b];
+        if (chain[a] != chain[b]) return chain[a] > chain[b];
+        return a < b;
+    });
+    std::vector<uint32_t> start(K, 0), need(K, 0);
+    for (uint32_t c = 0; c < K; ++c) {
+        uint32_t before = 0;
+        for (uint32_t d = c + 1; d < K; ++d) before += in_cls[d];
+        start[c] = before;
+        for (uint32_t d = 0; d <= c; ++d) need[c] += in_cls[d];
+    }
+    for (size_t i = 0; i < count; ++i)
+        if (epochs[i]) seqs_upto[pcls[i]] += ctxs[i]->cfg.n_sequences;
+    for (uint32_t c = 1; c < K; ++c) seqs_upto[c] += seqs_upto[c - 1];
+
+    // the problems' device records
+    std::vector<JobProblem> host(count);
+    for (size_t i = 0; i < count; ++i) {
+        pperm_ctx* x = ctxs[i];
+        JobProblem& J = host[i];
+        memset(&J, 0, sizeof(J));
+        J.desc = x->desc_dev;
+        J.sched = reinterpret_cast<const uint32_t*>(ws + L.sched[i]);
+        J.gver = reinterpret_cast<SumRec*>(ws + L.gver[i]);
+        J.flags = reinterpret_cast<uint32_t*>(ws + L.flags[i]);
+        J.epochs = epochs[i];
+        J.N = x->cfg.n_sequences;
+        J.p2 = pow2_at_least(J.N);
+        J.levels = log2u(J.p2);
+        J.cls = pcls[i];
+        J.lds = lds_of(x);
+    }
+    HIP_TRY(launch_fill_zero(ws, L.total, stream));     // state, counters, flags
+    HIP_TRY(hipMemcpyAsync(ws + L.probs, host.data(), count * sizeof(JobProblem), hipMemcpyHostToDevice,
+                           stream));
+    HIP_TRY(hipMemcpyAsync(ws + L.order, order.data(), order.size() * 4, hipMemcpyHostToDevice, stream));
+    for (size_t i = 0; i < count; ++i)
+        if (epochs[i])
+            HIP_TRY(hipMemcpyAsync(ws + L.sched[i], schedules[i], (size_t)epochs[i] * 4,
+                                   hipMemcpyHostToDevice, stream));
+
+    // one persistent launch per class, each on its own library stream with a
+    // share of the chip's LDS in proportion to its work times its LDS need
+    std::lock_guard<std::mutex> lock(g_batch_mutex);
+    DeviceStreams* ds = nullptr;
+    rc = batch_streams(device, &ds);
+    if (rc) return rc;
+    int cus = 0;
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
+    double demand = 0;
+    for (uint32_t c = 0; c < K; ++c) demand += work[c] * cls_lds[c];
+    HIP_TRY(hipEventRecord(ds->fork, stream));
+    for (uint32_t c = 0; c < K; ++c) {
+        int per_cu = 0;
+        HIP_TRY(job_occupancy(cls_lds[c], &per_cu));
+        if (per_cu < 1) return PPERM_EINVAL;
+        const uint64_t most = std::min<uint64_t>((uint64_t)per_cu * cus, seqs_upto[c]);
+        const double share = demand > 0 ? work[c] * cls_lds[c] / demand : 1.0;
+        uint64_t wgs = (uint64_t)(share * cus * (double)kLdsLimit / cls_lds[c]);
+        wgs = std::max<uint64_t>(wgs, std::min<uint64_t>(most, (uint64_t)cus));
+        wgs = std::min<uint64_t>(wgs, most);
+        JobArgs a;
+        memset(&a, 0, sizeof(a));
+        a.probs = reinterpret_cast<const JobProblem*>(ws + L.probs);
+        a.state = reinterpret_cast<JobState*>(ws + L.state);
+        a.order = reinterpret_cast<const uint32_t*>(ws + L.order);
+        a.counters = reinterpret_cast<uint32_t*>(ws + L.counters);
+        a.count = (uint32_t)order.size();
+        a.start = start[c];
+        a.cls = c;
+        a.need = need[c];
+        HIP_TRY(hipStreamWaitEvent(ds->s[c], ds->fork, 0));
+        HIP_TRY(launch_job(a, (uint32_t)wgs, cls_lds[c], ds->s[c]));
+        HIP_TRY(hipEventRecord(ds->join[c], ds->s[c]));
+    }
+    for (uint32_t c = 0; c < K; ++c) HIP_TRY(hipStreamWaitEvent(stream, ds->join[c], 0));
+    // the state a merge leaves: sums of the open epoch zero
+    for (size_t i = 0; i < count; ++i) {
+        pperm_ctx* x = ctxs[i];
+        if (!epochs[i]) continue;
+        HIP_TRY(launch_fill_zero(x->ws + x->lay.L, (size_t)x->cfg.n_sequences * x->lay.row * sizeof(SumRec),
+                                 stream));
+        uint64_t total = 0;
+        for (uint32_t e = 0; e < epochs[i]; ++e) total += schedules[i][e];
+        x->merged_tours += (uint64_t)x->cfg.n_sequences * total;
+    }
     return PPERM_OK;
 }
 

@@ -71,6 +71,7 @@ struct ProblemDesc {
     SumRec* L;            // [N][row]
     const SumRec* G;      // shared: [row]; independent: [N][row]
     const uint64_t* MG;   // shared: [1];   independent: [N]
+    uint64_t* HG;         // shared: [row]; independent: [N][row]
     uint32_t* m;          // [N]
     uint64_t* t;          // [N]
     uint64_t* stats;      // [N][STATS_WORDS]
@@ -84,7 +85,7 @@ struct ProblemDesc {
     uint32_t slots_log2;
     uint32_t lds_team_bytes;   // occupancy table + slot ids; the sums row follows
     uint32_t key0, key1;
-    uint32_t pad;
+    uint32_t pad[3];
 };
 
 // One problem's share of a launch: its tours, its step cap, and the index of
@@ -126,6 +127,48 @@ hipError_t launch_run(const RunArgs& a, uint32_t dim, uint32_t team_lanes, uint3
 hipError_t run_kernel_lds_ok(uint32_t dim, uint32_t team_lanes, uint32_t lds_bytes,
                              int* blocks_per_cu);
 hipError_t launch_merge_pass(const MergeArgs& a, hipStream_t s);
+// Device-side epoch chaining (pperm_run_job): one problem's part.
+struct JobProblem {
+    const ProblemDesc* desc;
+    const uint32_t* sched;    // tours per sequence of each epoch
+    SumRec* gver;             // [epochs][row]: pooled sums after each epoch's merge
+    uint32_t* flags;          // [p2] merge-tree node flags, zero between uses
+    uint32_t epochs;
+    uint32_t N;
+    uint32_t p2;              // N rounded up to a power of two
+    uint32_t levels;          // log2(p2)
+    uint32_t cls;             // LDS class
+    uint32_t lds;             // LDS bytes its walks need
+    uint32_t pad[2];
+};
+
+// Per-problem scheduling word: (epoch << 32) | sequences claimed in it; and
+// the tours of the epoch's finished sequences.
+struct JobState {
+    unsigned long long word;
+    uint32_t msum;
+    uint32_t pad;
+};
+
+enum : uint32_t { JOB_FINISHED0 = 0, JOB_PROGRESS = 4, JOB_ERROR = 5, JOB_COUNTER_WORDS = 8 };
+// records between consecutive per-epoch copies of the pooled sums (256 bytes)
+constexpr uint32_t JOB_GAP = 16;
+
+struct JobArgs {
+    const JobProblem* probs;
+    JobState* state;
+    const uint32_t* order;    // problem indices: classes descending, longest chain first
+    uint32_t* counters;       // JOB_* words
+    uint32_t count;
+    uint32_t start;           // first position of `order` this launch's waves may take
+    uint32_t cls;             // this launch's LDS class
+    uint32_t need;            // problems of classes <= cls
+};
+
+hipError_t launch_job(const JobArgs& a, uint32_t workgroups, uint32_t lds_bytes, hipStream_t s);
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
+hipError_t job_occupancy(uint32_t lds_bytes, int* blocks_per_cu);
+
 hipError_t launch_batch(const BatchArgs& b, uint32_t workgroups, uint32_t lds_bytes, hipStream_t s);
 hipError_t batch_occupancy(uint32_t lds_bytes, int* blocks_per_cu);
 hipError_t launch_merge_counts(const uint32_t* m, uint32_t N, uint64_t* MG, uint32_t* zero_m,

@@ -622,13 +622,17 @@ __device__ __forceinline__ uint64_t fields_lanes(uint64_t hb) {
 }
 
 // One sequence's `tours` tours against frozen pooled sums (the whole hot path
-// of one walk); run by one wavefront.  Every value below is wave-uniform
+// of one walk); run by one wavefront.  Gsrc: the pooled sums to read (the
+// problem's own, or an epoch's copy in a chained launch); fresh: the epoch
+// starts here, so the sequence's sums and tour count start from zero instead
+// of being read.  Returns the tours run.  Every value below is wave-uniform
 // except where a lane index enters (scan windows, Philox counters, deletions).
 // A step issues its occupancy reads first, evaluates the prune/enrich
 // arithmetic while they are in flight, and only then resolves the scan.
 template <int D>
-__device__ __forceinline__ void walk_sequence(const ProblemDesc& P, uint32_t tours, uint32_t cap,
-                                              uint32_t s, unsigned char* lds) {
+__device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t tours, uint32_t cap,
+                                                  uint32_t s, unsigned char* lds, const SumRec* Gsrc,
+                                                  bool fresh) {
     using L_ = Lat<D>;
     using Key = typename L_::Key;
     using F = Fields<D>;
@@ -689,12 +693,17 @@ __device__ __forceinline__ void walk_sequence(const ProblemDesc& P, uint32_t tou
 
     const size_t rb0 = (size_t)s * row;
     SumRec* __restrict__ Lrow = P.L + rb0;
-    const SumRec* Grow = shared_mode ? P.G : P.G + rb0;   // read with load_const
+    const SumRec* Grow = shared_mode ? Gsrc : Gsrc + rb0;   // read with load_const
     if (!shared_mode) MGs = ufirst64(P.MG[s]);
     const uint64_t t0 = ufirst64(P.t[s]);
     uint32_t tlo = (uint32_t)t0;               // tour index: its low word keys the random numbers
-    uint32_t m = ufirst(P.m[s]);
-    for (uint32_t i = (uint32_t)lane; i <= n_max; i += 64u) Ls[i] = load_global(Lrow + i);
+    uint32_t m = fresh ? 0u : ufirst(P.m[s]);
+    if (fresh) {
+        const SumRec z = {0.0, 0, 0u};
+        for (uint32_t i = (uint32_t)lane; i <= n_max; i += 64u) Ls[i] = z;
+    } else {
+        for (uint32_t i = (uint32_t)lane; i <= n_max; i += 64u) Ls[i] = load_global(Lrow + i);
+    }
     wave_fence();
     SumRec rec0 = Ls[0];
     // counters of this call, added to the sequence's totals at its end: the
@@ -942,6 +951,7 @@ __device__ __forceinline__ void walk_sequence(const ProblemDesc& P, uint32_t tou
     if (lane == ST_EVENTS || lane == ST_ENRICH || lane == ST_COPIES || lane == ST_PRUNES ||
         lane == ST_TRAPS)
         P.stats[(size_t)s * STATS_WORDS + lane] += cv;
+    return c_tours;
 }
 
 // Persistent launch over (problem, sequence) items of one or many problems:
@@ -971,9 +981,196 @@ __global__ void __launch_bounds__(64) batch_kernel(BatchArgs B) {
         // make every field (and so the whole walk's control flow) non-uniform
         const ProblemDesc P = load_const(E.desc);
         const uint32_t s = item - E.first_item;
-        if (P.dim == 2) walk_sequence<2>(P, E.tours, E.step_cap, s, lds);
-        else walk_sequence<3>(P, E.tours, E.step_cap, s, lds);
+        if (P.dim == 2) walk_sequence<2>(P, E.tours, E.step_cap, s, lds, P.G, false);
+        else walk_sequence<3>(P, E.tours, E.step_cap, s, lds, P.G, false);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Device-side epoch chaining.  Every problem runs its whole epoch schedule in
+// one persistent launch: a wave claims (problem, epoch, sequence) items, runs
+// the sequence's tours of that epoch, and then takes its sequence up the
+// problem's merge tree -- the aligned pairwise tree over sequences, padded
+// with zeros to p2 leaves -- as far as it is the second of two children to
+// arrive, adding its partner's partial row into the left child's row.  The
+// wave that completes the root adds the tree into the pooled sums (into a
+// fresh per-epoch copy, so that scalar loads of later epochs never meet a
+// line cached before it was written), adds the epoch's tours to M and
+// publishes the next epoch.  The result is the same as run + merge per epoch.
+// ---------------------------------------------------------------------------
+constexpr uint64_t JOB_IDLE_TICKS = 100000000ull * 120ull;   // 120 s at the 100 MHz clock
+
+__device__ __forceinline__ uint32_t job_finished(const JobArgs& A) {
+    uint32_t done = 0;
+    for (uint32_t c = 0; c <= A.cls; ++c)
+        done += __hip_atomic_load(&A.counters[JOB_FINISHED0 + c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return done;
+}
+
+// Lane 0 tries to claim the next sequence of problem pi's open epoch.
+__device__ __forceinline__ bool job_claim(const JobArgs& A, uint32_t pi, uint32_t epochs, uint32_t N,
+                                          uint32_t& e, uint32_t& s) {
+    unsigned long long w = __hip_atomic_load(&A.state[pi].word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int attempt = 0; attempt < 8; ++attempt) {
+        const uint32_t ee = (uint32_t)(w >> 32), cc = (uint32_t)w;
+        if (ee >= epochs || cc >= N) return false;
+        if (__hip_atomic_compare_exchange_strong(&A.state[pi].word, &w, w + 1ull, __ATOMIC_ACQUIRE,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            e = ee;
+            s = cc;
+            return true;
+        }
+    }
+    return false;
+}
+
+// The sequence's part of its epoch's merge, after its tours: sample counts,
+// tour count, and the climb up the merge tree.
+__device__ void job_merge(const JobArgs& A, const JobProblem& J, const ProblemDesc& P, uint32_t pi,
+                          uint32_t e, uint32_t s, uint32_t tours_run, unsigned char* lds) {
+    const int lane = (int)threadIdx.x;
+    const uint32_t row = P.row, n1 = P.n_max + 1u;
+    const SumRec* Ls = reinterpret_cast<const SumRec*>(lds + P.lds_team_bytes);
+    for (uint32_t n = (uint32_t)lane; n < n1; n += 64u)
+        __hip_atomic_fetch_add(&P.HG[n], (uint64_t)Ls[n].h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (lane == 0) {
+        __hip_atomic_fetch_add(&A.state[pi].msum, tours_run, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        P.m[s] = 0u;
+    }
+    uint32_t l = 0, i = s;
+    for (;;) {
+        if (l == J.levels) break;                         // at the root
+        if (((i ^ 1u) << l) < J.N) {
+            // the partner subtree has leaves: the second of the two goes on
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            uint32_t old = 0u;
+            if (lane == 0)
+                old = __hip_atomic_fetch_add(&J.flags[(J.p2 >> (l + 1u)) + (i >> 1)], 1u, __ATOMIC_ACQ_REL,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+            old = ufirst(__shfl(old, 0, 64));
+            if (old == 0u) return;                        // the partner will continue
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            if (lane == 0) J.flags[(J.p2 >> (l + 1u)) + (i >> 1)] = 0u;
+            SumRec* left = P.L + (size_t)((i & ~1u) << l) * row;
+            const SumRec* right = P.L + (size_t)((i | 1u) << l) * row;
+            for (uint32_t n = (uint32_t)lane; n < n1; n += 64u) {
+                const SumRec a = load_global(left + n);
+                const SumRec b = load_global(right + n);
+                const XF v = xf_add(xf_of(a), xf_of(b));
+                SumRec r;
+                r.m = v.m;
+                r.e = v.e;
+                r.h = 0u;
+                store_global(left + n, r);
+            }
+        }
+        // (no partner: the padded subtree adds +0, the node is this subtree)
+        l += 1u;
+        i >>= 1;
+    }
+    // root: pooled sums of the next epoch, then M, then publish
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    const SumRec* Gprev = (e == 0u) ? P.G : J.gver + (size_t)(e - 1u) * (row + JOB_GAP);
+    SumRec* Gnext = J.gver + (size_t)e * (row + JOB_GAP);
+    SumRec* Gctx = const_cast<SumRec*>(P.G);
+    for (uint32_t n = (uint32_t)lane; n < n1; n += 64u) {
+        const SumRec a = load_global(Gprev + n);
+        const SumRec b = load_global(P.L + n);            // the root's row is leaf 0's
+        const XF v = xf_add(xf_of(a), xf_of(b));
+        SumRec r;
+        r.m = v.m;
+        r.e = v.e;
+        r.h = 0u;
+        store_global(Gnext + n, r);
+        store_global(Gctx + n, r);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (lane == 0) {
+        const uint32_t msum = __hip_atomic_exchange(&A.state[pi].msum, 0u, __ATOMIC_ACQ_REL,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+        uint64_t* MG = const_cast<uint64_t*>(P.MG);
+        MG[0] += msum;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_store(&A.state[pi].word, (unsigned long long)(e + 1u) << 32, __ATOMIC_RELEASE,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        if (e + 1u == J.epochs)
+            __hip_atomic_fetch_add(&A.counters[JOB_FINISHED0 + J.cls], 1u, __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+__global__ void __launch_bounds__(64) job_kernel(JobArgs A) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    const int lane = (int)threadIdx.x;
+    uint64_t idle_since = __builtin_amdgcn_s_memrealtime();
+    uint32_t seen_progress = 0u;
+    for (;;) {
+        // ---- claim: the first problem (in priority order) with an open item ----
+        bool got = false;
+        uint32_t pi = 0u, e = 0u, s = 0u;
+        for (uint32_t b = A.start; b < A.count && !got; b += 64u) {
+            const uint32_t idx = b + (uint32_t)lane;
+            uint32_t mine = 0u;
+            bool open = false;
+            if (idx < A.count) {
+                mine = A.order[idx];
+                const JobProblem& J = A.probs[mine];
+                const unsigned long long w =
+                    __hip_atomic_load(&A.state[mine].word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                open = (uint32_t)(w >> 32) < J.epochs && (uint32_t)w < J.N;
+            }
+            uint64_t cand = __ballot(open);
+            while (cand != 0u && !got) {
+                const uint32_t f = (uint32_t)__ffsll((unsigned long long)cand) - 1u;
+                cand &= cand - 1u;
+                const uint32_t p = lane_value(mine, f);
+                uint32_t ok = 0u, ce = 0u, cs = 0u;
+                if (lane == 0) {
+                    const JobProblem& J = A.probs[p];
+                    ok = job_claim(A, p, J.epochs, J.N, ce, cs) ? 1u : 0u;
+                }
+                ok = ufirst(__shfl(ok, 0, 64));
+                if (ok) {
+                    got = true;
+                    pi = p;
+                    e = ufirst(__shfl(ce, 0, 64));
+                    s = ufirst(__shfl(cs, 0, 64));
+                }
+            }
+        }
+        if (!got) {
+            if (job_finished(A) >= A.need) break;
+            if (__hip_atomic_load(&A.counters[JOB_ERROR], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+            const uint32_t prog =
+                __hip_atomic_load(&A.counters[JOB_PROGRESS], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint64_t now = __builtin_amdgcn_s_memrealtime();
+            if (prog != seen_progress) {
+                seen_progress = prog;
+                idle_since = now;
+            } else if (now - idle_since > JOB_IDLE_TICKS) {
+                break;                                    // backstop: leave the rest to others
+            }
+            __builtin_amdgcn_s_sleep(127);
+            continue;
+        }
+        // ---- the item: the sequence's tours of this epoch, then its merge part ----
+        const JobProblem J = load_const(A.probs + pi);
+        const ProblemDesc P = load_const(J.desc);
+        const uint32_t tours = J.sched[e];
+        uint64_t cap64 = 4096ull * tours * (P.n_max + 1ull);
+        const uint32_t cap = cap64 > (1ull << 31) ? (1u << 31) : (uint32_t)cap64;
+        const SumRec* Gsrc = (e == 0u) ? P.G : J.gver + (size_t)(e - 1u) * (P.row + JOB_GAP);
+        const uint32_t ran = (P.dim == 2) ? walk_sequence<2>(P, tours, cap, s, lds, Gsrc, true)
+                                          : walk_sequence<3>(P, tours, cap, s, lds, Gsrc, true);
+        job_merge(A, J, P, pi, e, s, ran, lds);
+        if (lane == 0)
+            __hip_atomic_fetch_add(&A.counters[JOB_PROGRESS], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        idle_since = __builtin_amdgcn_s_memrealtime();
+    }
+}
+
+__global__ void __launch_bounds__(256) fill_zero_kernel(uint32_t* p, size_t words) {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < words; i += (size_t)gridDim.x * 256) p[i] = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -1174,6 +1371,24 @@ hipError_t launch_init_state(uint64_t* stats, uint32_t N, void* zero_base, size_
 
 hipError_t launch_batch(const BatchArgs& b, uint32_t workgroups, uint32_t lds_bytes, hipStream_t s) {
     hipLaunchKernelGGL(batch_kernel, dim3(workgroups), dim3(64), lds_bytes, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_job(const JobArgs& a, uint32_t workgroups, uint32_t lds_bytes, hipStream_t s) {
+    hipLaunchKernelGGL(job_kernel, dim3(workgroups), dim3(64), lds_bytes, s, a);
+    return hipGetLastError();
+}
+
+hipError_t job_occupancy(uint32_t lds_bytes, int* blocks_per_cu) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, job_kernel, 64, lds_bytes);
+}
+
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
+    const size_t words = bytes / 4;
+    if (words == 0) return hipSuccess;
+    uint32_t blocks = (uint32_t)((words + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(blocks), dim3(256), 0, s, (uint32_t*)p, words);
     return hipGetLastError();
 }
 

@@ -170,6 +170,27 @@ class Batch:
                    "pperm_run_batch")
 
 
+def run_job(problems, schedules, stream=None):
+    """Every problem through its whole epoch schedule (tours per epoch, a merge
+    after each) in persistent launches that chain epochs on the device."""
+    lib = _abi.load()
+    count = len(problems)
+    device = problems[0].device
+    ctxs = (ctypes.c_void_p * count)(*[p._ctx for p in problems])
+    epochs = (ctypes.c_uint32 * count)(*[len(s) for s in schedules])
+    arrays = [(ctypes.c_uint32 * max(1, len(s)))(*s) for s in schedules]
+    sched = (ctypes.POINTER(ctypes.c_uint32) * count)(*[ctypes.cast(a, ctypes.POINTER(ctypes.c_uint32))
+                                                        for a in arrays])
+    nbytes = ctypes.c_size_t()
+    _abi.check(lib.pperm_job_workspace_bytes(ctxs, epochs, count, ctypes.byref(nbytes)), "pperm_job_workspace_bytes")
+    with torch.cuda.device(device):
+        stream = stream if stream is not None else torch.cuda.current_stream(device)
+        ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=device)
+        _abi.check(lib.pperm_run_job(ctxs, sched, epochs, count, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                     ctypes.c_void_p(stream.cuda_stream)), "pperm_run_job")
+    return ws
+
+
 def run_schedules(problems, schedules, batch=None):
     """Run each problem through its own epoch schedule (tours per epoch, a merge
     after each), all problems of an epoch index in one batched launch."""
