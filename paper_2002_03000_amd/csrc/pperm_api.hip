@@ -711,6 +711,9 @@ int pperm_run_job(pperm_ctx* const* ctxs, const uint32_t* const* schedules, cons
         J.levels = log2u(J.p2);
         J.cls = pcls[i];
         J.lds = lds_of(x);
+        // chains within a factor 2, 4, 8 of the longest get priorities 3, 2, 1
+        const double top = *std::max_element(chain.begin(), chain.end());
+        J.prio = (top > 0 && chain[i] * 2 >= top) ? 3u : (chain[i] * 4 >= top) ? 2u : (chain[i] * 8 >= top) ? 1u : 0u;
     }
     HIP_TRY(launch_fill_zero(ws, L.total, stream));     // state, counters, flags
     HIP_TRY(hipMemcpyAsync(ws + L.probs, host.data(), count * sizeof(JobProblem), hipMemcpyHostToDevice,

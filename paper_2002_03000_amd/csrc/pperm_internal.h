@@ -139,7 +139,8 @@ struct JobProblem {
     uint32_t levels;          // log2(p2)
     uint32_t cls;             // LDS class
     uint32_t lds;             // LDS bytes its walks need
-    uint32_t pad[2];
+    uint32_t prio;            // issue priority 0..3 of its waves (longest chains highest)
+    uint32_t pad;
 };
 
 // Per-problem scheduling word: (epoch << 32) | sequences claimed in it; and

@@ -1157,12 +1157,17 @@ __global__ void __launch_bounds__(64) job_kernel(JobArgs A) {
         const JobProblem J = load_const(A.probs + pi);
         const ProblemDesc P = load_const(J.desc);
         const uint32_t tours = J.sched[e];
+        // the job ends with its longest chain of epochs: its waves issue first
+        if (J.prio == 3u) __builtin_amdgcn_s_setprio(3);
+        else if (J.prio == 2u) __builtin_amdgcn_s_setprio(2);
+        else if (J.prio == 1u) __builtin_amdgcn_s_setprio(1);
         uint64_t cap64 = 4096ull * tours * (P.n_max + 1ull);
         const uint32_t cap = cap64 > (1ull << 31) ? (1u << 31) : (uint32_t)cap64;
         const SumRec* Gsrc = (e == 0u) ? P.G : J.gver + (size_t)(e - 1u) * (P.row + JOB_GAP);
         const uint32_t ran = (P.dim == 2) ? walk_sequence<2>(P, tours, cap, s, lds, Gsrc, true)
                                           : walk_sequence<3>(P, tours, cap, s, lds, Gsrc, true);
         job_merge(A, J, P, pi, e, s, ran, lds);
+        __builtin_amdgcn_s_setprio(0);
         if (lane == 0)
             __hip_atomic_fetch_add(&A.counters[JOB_PROGRESS], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         idle_since = __builtin_amdgcn_s_memrealtime();
