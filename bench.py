@@ -69,6 +69,7 @@ WORKLOADS = {
     "plain2d": workloads.PLAIN_2D,
     "batched": None,          # the 256-problem mix, see run_batched()
     "served": None,           # the Poisson job stream, see run_served()
+    "compare": None,          # Algorithm 1 vs Algorithm 2, see run_compare()
 }
 
 
@@ -112,6 +113,9 @@ def main():
     ap.add_argument("--problems", type=int, default=0, help="batched: use the first P problems of the mix")
     ap.add_argument("--lockstep", action="store_true",
                     help="batched: lock-step rounds of batched calls instead of device-chained epochs")
+    ap.add_argument("--compare-n", default="1,2,12,64", help="compare: sequence counts")
+    ap.add_argument("--compare-s", default="1,10,100,1000,10000", help="compare: tours per sequence")
+    ap.add_argument("--compare-replicas", type=int, default=8, help="compare: independent runs per cell")
     ap.add_argument("--serve-duration", type=float, default=60.0, help="served: arrival window (s)")
     ap.add_argument("--serve-rate", type=float, default=50.0, help="served: arrivals per second")
     ap.add_argument("--serve-cap", type=int, default=4096, help="served: tour cap per job")
@@ -142,6 +146,9 @@ def main():
         return
     if args.workload == "served":
         run_served(args)
+        return
+    if args.workload == "compare":
+        run_compare(args)
         return
 
     import numpy as np
@@ -524,6 +531,115 @@ def run_served(args, plain_budget_s=30.0):
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline_mix([j.problem for j in jobs])
+    print(json.dumps(line), flush=True)
+
+
+def tour_schedule(S, T=64):
+    """S tours per sequence as epochs: 1, 1, 2, 4, ... doubling up to T, then T,
+    the last epoch cut so that the total is exactly S."""
+    out, head = [], [1]
+    while 2 * sum(head) <= T:
+        head.append(sum(head))
+    for t in head + [T] * (S // T + 1):
+        if sum(out) >= S:
+            break
+        out.append(min(t, S - sum(out)))
+    return out
+
+
+def run_compare(args):
+    """Algorithm 1 (independent sequences, estimates combined by the arithmetic
+    mean of eqn (7) and by the geometric mean) against Algorithm 2 (shared
+    running averages) on the square lattice at n_max = 500: T_M of eqn (9)
+    against a reference run 15x longer than the longest compared run, and the
+    band width E of the eqn-(15) fit, for N sequences and S tours per
+    sequence (the layout of the paper's Tables 3 and 4)."""
+    import numpy as np
+    import torch
+    from paper_2002_03000_amd import ParallelFlatPERM, analysis, run_schedules
+
+    torch.cuda.set_device(0)
+    n_max = 500
+    ref_p = workloads.PARALLEL_2D
+    ref = ParallelFlatPERM(2, n_max, ref_p.n_sequences, 900_001, mode="shared")
+    for T in ref_p.schedule():
+        ref.run_tours(T)
+        ref.merge_epoch()
+    log_best, _, ref_tours = ref.estimates()
+    ref.close()
+    ref_fit = analysis.ratio_fit(log_best)
+    _log(f"reference: {ref_tours} tours, mu {ref_fit['mu']:.6f}, gamma {ref_fit['gamma']:.4f}")
+
+    Ns = [int(x) for x in args.compare_n.split(",")]
+    Ss = [int(x) for x in args.compare_s.split(",")]
+    R = args.compare_replicas
+    # every (algorithm, N, S, replica) is one problem; all of them run together
+    # as lock-step batched rounds (each problem's epochs exactly as alone)
+    cells, probs, scheds = [], [], []
+    seed = 910_000
+    for N in Ns:
+        for S in Ss:
+            for mode in ("independent", "shared"):
+                if mode == "shared" and N == 1:
+                    continue                      # one sequence: the two algorithms coincide
+                for r in range(R):
+                    seed += 1
+                    cells.append((mode, N, S, r))
+                    probs.append(ParallelFlatPERM(2, n_max, N, seed, mode=mode, stream_id=len(probs)))
+                    scheds.append(tour_schedule(S))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run_schedules(probs, scheds)
+    done = torch.cuda.Event()
+    done.record()
+    last = t0
+    while not done.query():
+        time.sleep(0.5)
+        if time.perf_counter() - last > 10:
+            last = time.perf_counter()
+            _log(f"compare: {len(probs)} problems running, {last - t0:.0f} s")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    steps = {"independent": 0, "shared": 0}
+    results = {}
+    for (mode, N, S, r), g in zip(cells, probs):
+        steps[mode] += g.stats()["steps"]
+        lc, _, _ = g.estimates()
+        if mode == "independent":
+            per = g.sequence_log_estimates()
+            ests = {"alg1_mean": lc, "alg1_geometric": analysis.combine_geometric(per)}
+        else:
+            ests = {"alg2": lc}
+        for kind, est in ests.items():
+            fin = np.isfinite(est)
+            top = int(np.max(np.nonzero(fin)[0])) if fin.any() else 0
+            tm = analysis.total_abs_error(log_best, est, M=top) if top > 0 else float("nan")
+            e = analysis.ratio_fit(est, n_max=top)["E"] if top > 3 else float("nan")
+            results.setdefault((kind, N, S), []).append((tm, e, top))
+        g.close()
+    table = {"T_M": {}, "T_M_se": {}, "E": {}, "E_se": {}, "sampled_lengths_min": {}}
+    for (kind, N, S), vals in sorted(results.items()):
+        v = np.array(vals, dtype=np.float64)
+        for name, col in (("T_M", 0), ("E", 1)):
+            x = v[:, col]
+            table[name].setdefault(kind, {}).setdefault(f"N={N}", {})[f"S={S}"] = float(np.nanmean(x))
+            table[name + "_se"].setdefault(kind, {}).setdefault(f"N={N}", {})[f"S={S}"] = \
+                float(np.nanstd(x, ddof=1) / np.sqrt(np.sum(np.isfinite(x)))) if len(x) > 1 else None
+        table["sampled_lengths_min"].setdefault(kind, {}).setdefault(f"N={N}", {})[f"S={S}"] = int(v[:, 2].min())
+    line = {
+        "metric": "T_M (eqn 9) and band width E (eqn 15 fit): Algorithm 1 vs Algorithm 2, 1 GPU",
+        "unit": "log units",
+        "n_gpus": 1,
+        "data": "synthetic (walks grown from parameters)",
+        "config": {"workload": f"square lattice, n_max={n_max}, N in {Ns}, S tours per sequence in {Ss}, "
+                               f"{R} replicas per cell (all cells in one set of batched rounds); "
+                               f"reference: Algorithm 2, N=4096, {ref_tours} tours",
+                   "reference_fit": ref_fit, "replicas": R},
+        "tables": table,
+        "walk_steps": {"alg1": steps["independent"], "alg2": steps["shared"]},
+        "walk_steps_per_s_all": (steps["independent"] + steps["shared"]) / elapsed,
+        "seconds": elapsed,
+    }
     print(json.dumps(line), flush=True)
 
 

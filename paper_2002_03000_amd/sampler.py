@@ -64,6 +64,17 @@ class ParallelFlatPERM:
         return lc, hist, int(tours.value)
 
     # -- inspection -------------------------------------------------------------------
+    def sequence_log_estimates(self):
+        """Algorithm 1: each sequence's own log c_n estimate, shape (N, n_max + 1)
+        (read back from the merged state; -inf where a sequence has no sample)."""
+        if self.mode != "independent":
+            raise ValueError("per-sequence estimates exist in independent mode only")
+        n1 = self.n_max + 1
+        rec = self.records("G")[:, :n1]
+        MG = self.view("MG").cpu().numpy().view(np.uint64).astype(np.float64)
+        with np.errstate(divide="ignore"):
+            return np.log(rec["m"]) + rec["e"] * np.log(2.0) - np.log(MG)[:, None]
+
     def error_estimate(self):
         """(relative error estimate of c_{n_max} from 16 sequence groups, log group estimates)."""
         rel = ctypes.c_double()
