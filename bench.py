@@ -110,6 +110,7 @@ def main():
     ap.add_argument("--epochs", type=int, default=0, help="override the epoch count (profiling)")
     ap.add_argument("--walks-per-wave", type=int, default=0)
     ap.add_argument("--hash-slots", type=int, default=0)
+    ap.add_argument("--autotune", action="store_true", help="pick the launch shape by short trial runs first")
     ap.add_argument("--problems", type=int, default=0, help="batched: use the first P problems of the mix")
     ap.add_argument("--lockstep", action="store_true",
                     help="batched: lock-step rounds of batched calls instead of device-chained epochs")
@@ -160,6 +161,12 @@ def main():
         p = p.scaled(epochs=args.epochs)
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    tuning = None
+    if args.autotune:
+        # launch shape from short trial runs, before and outside the timed region
+        from paper_2002_03000_amd import autotune
+        best, tuning = autotune(p.dim, p.n_max, p.n_sequences, mode=p.mode, trial=tuple(p.schedule()[:5]))
+        args.walks_per_wave, args.hash_slots = best["walks_per_wave"], best["hash_slots"]
 
     def make(seed):
         return ParallelFlatPERM(p.dim, p.n_max, p.n_sequences, seed, mode=p.mode,
@@ -229,7 +236,7 @@ def main():
                    "n_sequences": p.n_sequences, "tours_per_epoch": p.tours_per_epoch,
                    "epochs": len(sched), "schedule": sched[:len(sched) - p.epochs + 2],
                    "walk_steps_per_job": steps_total // args.steps,
-                   "launch": shape},
+                   "launch": shape, "autotune": tuning},
         "cn_rel_err_nmax": rel_err,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
                      "frac": achieved / ALU_PEAK_TOPS,

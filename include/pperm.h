@@ -157,6 +157,17 @@ int pperm_batch_workspace_bytes(size_t count, size_t* bytes);
 int pperm_run_batch(pperm_ctx* const* ctxs, size_t count, const uint32_t* tours_each,
                     void* d_workspace, size_t bytes, void* hip_stream);
 
+/* One epoch -- pperm_run_tours(tours) then pperm_merge_epoch -- captured once
+ * as a HIP graph and replayed: each pperm_epoch_graph_launch enqueues the
+ * whole epoch on the context's stream with one launch, with exactly the
+ * effect of the two calls.  Capture runs on a private stream; the context
+ * must have no unmerged tours (ESTATE), at creation and at each launch.  The
+ * graph belongs to its context and must be destroyed before it. */
+typedef struct pperm_graph pperm_graph;
+int pperm_epoch_graph_create(pperm_ctx* ctx, uint32_t tours, pperm_graph** out);
+int pperm_epoch_graph_launch(pperm_graph* graph);
+int pperm_epoch_graph_destroy(pperm_graph* graph);
+
 /* Device bytes of the scratch pperm_run_job needs for these contexts and
  * epoch counts. */
 int pperm_job_workspace_bytes(pperm_ctx* const* ctxs, const uint32_t* epochs, size_t count,

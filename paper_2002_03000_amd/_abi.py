@@ -70,6 +70,9 @@ SIGNATURES = {
     "pperm_merge_epoch": (_int, [_vp]),
     "pperm_batch_workspace_bytes": (_int, [_sz, _c.POINTER(_sz)]),
     "pperm_run_batch": (_int, [_c.POINTER(_vp), _sz, _c.POINTER(_u32), _vp, _sz, _vp]),
+    "pperm_epoch_graph_create": (_int, [_vp, _u32, _c.POINTER(_vp)]),
+    "pperm_epoch_graph_launch": (_int, [_vp]),
+    "pperm_epoch_graph_destroy": (_int, [_vp]),
     "pperm_job_workspace_bytes": (_int, [_c.POINTER(_vp), _c.POINTER(_u32), _sz, _c.POINTER(_sz)]),
     "pperm_run_job": (_int, [_c.POINTER(_vp), _c.POINTER(_c.POINTER(_u32)), _c.POINTER(_u32), _sz, _vp, _sz, _vp]),
     "pperm_estimates": (_int, [_vp, _c.POINTER(_c.c_double), _c.POINTER(_u64), _c.POINTER(_u64), _sz]),

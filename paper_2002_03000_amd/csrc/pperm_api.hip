@@ -546,6 +546,81 @@ int pperm_run_batch(pperm_ctx* const* ctxs, size_t count, const uint32_t* tours_
     return PPERM_OK;
 }
 
+// ---- one epoch as a captured HIP graph -------------------------------------------
+struct pperm_graph {
+    pperm_ctx* ctx;
+    uint32_t tours;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+extern "C" int pperm_epoch_graph_create(pperm_ctx* x, uint32_t tours, pperm_graph** out) {
+    if (!x || !out || tours == 0) return PPERM_EINVAL;
+    *out = nullptr;
+    if (x->open_tours != 0) return PPERM_ESTATE;
+    hipStream_t cap = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    // capture on a private stream (the legacy default stream cannot be
+    // captured); the context's counters are restored afterwards
+    const hipStream_t keep = x->stream;
+    const uint64_t merged = x->merged_tours, open = x->open_tours;
+    hipGraph_t g = nullptr;
+    int rc = PPERM_OK;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed);
+    if (e == hipSuccess) {
+        x->stream = cap;
+        rc = pperm_run_tours(x, tours);
+        if (rc == PPERM_OK) rc = pperm_merge_epoch(x);
+        x->stream = keep;
+        e = hipStreamEndCapture(cap, &g);
+    }
+    x->merged_tours = merged;
+    x->open_tours = open;
+    (void)hipStreamDestroy(cap);
+    if (e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return device_error(e, "graph capture");
+    }
+    if (rc) {
+        (void)hipGraphDestroy(g);
+        return rc;
+    }
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return device_error(e, "graph instantiate");
+    }
+    pperm_graph* G = new (std::nothrow) pperm_graph{x, tours, g, exec};
+    if (!G) {
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(g);
+        return PPERM_ENOMEM;
+    }
+    *out = G;
+    return PPERM_OK;
+}
+
+extern "C" int pperm_epoch_graph_launch(pperm_graph* G) {
+    if (!G) return PPERM_EINVAL;
+    pperm_ctx* x = G->ctx;
+    if (x->open_tours != 0) return PPERM_ESTATE;
+    const uint64_t N = x->cfg.n_sequences;
+    const uint64_t add = (x->cfg.mode == PPERM_SHARED) ? N * G->tours : G->tours;
+    if (x->merged_tours + add > 0xFFFFFFFFull) return PPERM_EOVERFLOW;
+    HIP_TRY(hipGraphLaunch(G->exec, x->stream));
+    x->merged_tours += add;
+    return PPERM_OK;
+}
+
+extern "C" int pperm_epoch_graph_destroy(pperm_graph* G) {
+    if (!G) return PPERM_EINVAL;
+    (void)hipGraphExecDestroy(G->exec);
+    (void)hipGraphDestroy(G->graph);
+    delete G;
+    return PPERM_OK;
+}
+
 // ---- device-side epoch chaining ----------------------------------------------
 namespace {
 

@@ -64,6 +64,10 @@ class ParallelFlatPERM:
         return lc, hist, int(tours.value)
 
     # -- inspection -------------------------------------------------------------------
+    def epoch_graph(self, tours_per_sequence):
+        """A captured epoch (run_tours + merge_epoch) to replay with .launch()."""
+        return EpochGraph(self, tours_per_sequence)
+
     def sequence_log_estimates(self):
         """Algorithm 1: each sequence's own log c_n estimate, shape (N, n_max + 1)
         (read back from the merged state; -inf where a sequence has no sample)."""
@@ -216,6 +220,31 @@ def run_schedules(problems, schedules, batch=None):
     return batch
 
 
+class EpochGraph:
+    """One epoch of a problem captured as a HIP graph (see pperm_epoch_graph_create)."""
+
+    def __init__(self, problem, tours):
+        self.problem = problem
+        g = ctypes.c_void_p()
+        _abi.check(problem._lib.pperm_epoch_graph_create(problem._ctx, int(tours), ctypes.byref(g)),
+                   "pperm_epoch_graph_create")
+        self._g = g
+
+    def launch(self):
+        _abi.check(self.problem._lib.pperm_epoch_graph_launch(self._g), "pperm_epoch_graph_launch")
+
+    def close(self):
+        if getattr(self, "_g", None):
+            self.problem._lib.pperm_epoch_graph_destroy(self._g)
+            self._g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 JOB_STATES = {_abi.JOB_QUEUED: "queued", _abi.JOB_ACTIVE: "active", _abi.JOB_DONE: "done",
               _abi.JOB_FAILED: "failed"}
 
@@ -312,3 +341,48 @@ def pool_script(pool_bytes, ops):
     used = lib.pperm_pool_script(int(pool_bytes), ops.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), len(ops),
                                  offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
     return offs, int(used)
+
+
+def autotune(dim, n_max, n_sequences, mode="shared", trial=(1, 1, 2, 4, 8), seed=0x5EED,
+             walks_per_wave=(1, 2, 4, 8), slot_factors=(1, 2), device=None):
+    """Choose the launch shape (walks per wave, hash slots) for a configuration
+    by timing a short trial schedule of every candidate on a scratch problem
+    with its own seed.  Launch shapes never change a result, so the choice
+    is free.  Returns (best, table): best = {"walks_per_wave", "hash_slots",
+    "ms"}, table = one such dict per candidate that fits the device."""
+    device = torch.device(device if device is not None else "cuda")
+    s0 = 64
+    while s0 < 2 * (n_max + 1):
+        s0 *= 2
+    table = []
+    warmed = False
+    for wpw in walks_per_wave:
+        for f in slot_factors:
+            slots = s0 * f
+            try:
+                g = ParallelFlatPERM(dim, n_max, n_sequences, seed, mode=mode, hash_slots=slots,
+                                     walks_per_wave=wpw, device=device)
+            except _abi.PPermError:
+                continue                      # does not fit (LDS or lane count)
+            if not warmed:
+                for T in trial[:2]:
+                    g.run_tours(T)
+                    g.merge_epoch()
+                g.sync()
+                g.close()
+                g = ParallelFlatPERM(dim, n_max, n_sequences, seed, mode=mode, hash_slots=slots,
+                                     walks_per_wave=wpw, device=device)
+                warmed = True
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(g.stream)
+            for T in trial:
+                g.run_tours(T)
+                g.merge_epoch()
+            b.record(g.stream)
+            g.sync()
+            table.append({"walks_per_wave": wpw, "hash_slots": slots, "ms": a.elapsed_time(b)})
+            g.close()
+    if not table:
+        raise RuntimeError("no launch shape fits this configuration")
+    best = min(table, key=lambda r: r["ms"])
+    return best, table
