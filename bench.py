@@ -121,8 +121,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=50.0, help="served: arrivals per second")
     ap.add_argument("--serve-cap", type=int, default=4096, help="served: tour cap per job")
     ap.add_argument("--serve-target", type=float, default=1e-3, help="served: relative-error target")
-    ap.add_argument("--serve-pool-gib", type=float, default=8.0)
-    ap.add_argument("--serve-max-sequences", type=int, default=32768)
+    ap.add_argument("--serve-pool-gib", type=float, default=64.0)
+    ap.add_argument("--serve-max-sequences", type=int, default=262144)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-digest", action="store_true",
                     help="print the digest that keys the committed counter summaries")

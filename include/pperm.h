@@ -189,6 +189,27 @@ int pperm_job_workspace_bytes(pperm_ctx* const* ctxs, const uint32_t* epochs, si
 int pperm_run_job(pperm_ctx* const* ctxs, const uint32_t* const* schedules, const uint32_t* epochs,
                   size_t count, void* d_workspace, size_t bytes, void* hip_stream);
 
+/* Stop rule of a chained problem: stop at the first merge where
+ * pperm_error_estimate is at most target_rel_err (> 0 needs
+ * PPERM_FLAG_GROUP_STATS), or where the pooled tours M reach tour_cap (0:
+ * no cap); target checked first. */
+typedef struct pperm_job_limits {
+    double target_rel_err;
+    uint64_t tour_cap;
+} pperm_job_limits;
+
+/* pperm_run_job with, per problem, the stop rule of limits[i] (NULL: none)
+ * evaluated on the device after every merge, and a time slice: after slice_us
+ * microseconds (0: none) no epoch starts, the epochs under way finish.  The
+ * call synchronises and writes epochs_done[i] (epochs run and merged), stop[i]
+ * (0, 1 target, 2 cap; may be NULL) and rel_err[i] (the estimate after the
+ * last merge, +inf when undefined or with no stop rule; may be NULL).  A
+ * problem's result is the same however its epochs are split over calls. */
+int pperm_run_job_sliced(pperm_ctx* const* ctxs, const uint32_t* const* schedules, const uint32_t* epochs,
+                         size_t count, void* d_workspace, size_t bytes, void* hip_stream,
+                         const pperm_job_limits* limits, uint32_t slice_us, uint32_t* epochs_done,
+                         uint32_t* stop, double* rel_err);
+
 /* Synchronise the stream and read the merged state into caller-owned host
  * buffers of `len` >= n_max + 1 entries:
  *   log_cn[n] = log of the estimate of c_n (eqn (4); the mean of eqn (7) in
@@ -229,11 +250,12 @@ int pperm_destroy(pperm_ctx* ctx);
 
 /* ---- serving: continuous batching of sampling jobs ---------------------------
  * A server owns a device memory pool (caller-owned, carved by a first-fit
- * allocator) and a FIFO of submitted jobs.  Each pperm_server_step admits queued
- * jobs in arrival order while their workspace (pperm_workspace_bytes) fits in
- * the pool and the active sequences stay within max_active_sequences, runs the
- * next epoch of every active job in one pperm_run_batch, merges each, and
- * retires every job whose stop rule holds after that merge.  A job's results
+ * allocator; an eighth of it is kept for the launches) and a FIFO of submitted
+ * jobs.  Each pperm_server_step admits queued jobs in arrival order while their
+ * workspace (pperm_workspace_bytes) fits in the pool and the active sequences
+ * stay within max_active_sequences, then runs one time slice of chained epochs
+ * (pperm_run_job_sliced) in which every active job advances at its own pace and
+ * stops at the first merge where its stop rule holds; stopped jobs retire.  A job's results
  * depend only on its own description, never on what else is served with it.
  * Not thread-safe. */
 typedef struct pperm_server pperm_server;
@@ -244,7 +266,7 @@ typedef struct pperm_job {
     uint32_t n_max;
     uint32_t n_sequences;      /* N >= 16 for the relative-error stop rule                */
     uint64_t seed;
-    uint32_t mode;             /* PPERM_SHARED / PPERM_INDEPENDENT / PPERM_ROSENBLUTH     */
+    uint32_t mode;             /* PPERM_SHARED or PPERM_ROSENBLUTH                        */
     uint32_t stream_id;
     uint32_t tours_per_epoch;  /* T >= 1                                                  */
     uint32_t warmup;           /* 1: first epochs of 1, 1, 2, 4, ... tours (doubling while
@@ -298,6 +320,10 @@ int pperm_server_result(pperm_server* srv, uint64_t id, double* log_cn, uint64_t
 
 /* Forget a retired job's results. */
 int pperm_server_release(pperm_server* srv, uint64_t id);
+
+/* Length of a step's time slice in microseconds (default 100000): after it no
+ * job starts another epoch in that step (results never depend on it). */
+int pperm_server_set_slice(pperm_server* srv, uint32_t slice_us);
 
 /* Jobs waiting and active, and the pool bytes in use. */
 int pperm_server_counts(pperm_server* srv, uint32_t* queued, uint32_t* active, uint64_t* pool_used);

@@ -230,12 +230,23 @@ class Oracle:
     def error_estimate(self):
         """Relative error estimate of c_{n_max} from the 16 group sums: the
         sample standard deviation of the group averages A_k / C_k over 4 times
-        their mean (+inf while a group is empty or has no weight at n_max)."""
+        their mean (+inf while a group is empty or has no weight at n_max).
+        The averages are taken relative to the largest group exponent,
+        g_k = ldexp(m_k / C_k, e_k - e_max), and summed in group order, so the
+        value is a fixed sequence of correctly rounded operations."""
         if np.any(self.gtours == 0) or np.any(self.gsum["m"] == 0.0):
             return math.inf
-        lg = xf_log(self.gsum) - np.log(self.gtours.astype(np.float64))
-        x = np.exp(lg - lg.max())
-        return float(np.std(x, ddof=1) / (4.0 * np.mean(x)))
+        e_top = int(self.gsum["e"].max())
+        g = [math.ldexp(float(self.gsum["m"][k]) / float(self.gtours[k]), int(self.gsum["e"][k]) - e_top)
+             for k in range(GROUPS)]
+        total = 0.0
+        for x in g:
+            total += x
+        mean = total / GROUPS
+        ss = 0.0
+        for x in g:
+            ss += (x - mean) * (x - mean)
+        return math.sqrt(ss / (GROUPS - 1)) / (4.0 * mean)
 
     def walk_steps(self):
         return int(self.stats["steps"].sum())

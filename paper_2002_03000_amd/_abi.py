@@ -53,6 +53,10 @@ class Job(ctypes.Structure):
                 ("tour_cap", ctypes.c_uint64)]
 
 
+class JobLimits(ctypes.Structure):
+    _fields_ = [("target_rel_err", ctypes.c_double), ("tour_cap", ctypes.c_uint64)]
+
+
 class JobInfo(ctypes.Structure):
     _fields_ = [("state", ctypes.c_uint32), ("error", ctypes.c_int32),
                 ("epochs", ctypes.c_uint32), ("stop", ctypes.c_uint32),
@@ -75,6 +79,9 @@ SIGNATURES = {
     "pperm_epoch_graph_destroy": (_int, [_vp]),
     "pperm_job_workspace_bytes": (_int, [_c.POINTER(_vp), _c.POINTER(_u32), _sz, _c.POINTER(_sz)]),
     "pperm_run_job": (_int, [_c.POINTER(_vp), _c.POINTER(_c.POINTER(_u32)), _c.POINTER(_u32), _sz, _vp, _sz, _vp]),
+    "pperm_run_job_sliced": (_int, [_c.POINTER(_vp), _c.POINTER(_c.POINTER(_u32)), _c.POINTER(_u32), _sz, _vp, _sz,
+                                    _vp, _c.POINTER(JobLimits), _u32, _c.POINTER(_u32), _c.POINTER(_u32),
+                                    _c.POINTER(_c.c_double)]),
     "pperm_estimates": (_int, [_vp, _c.POINTER(_c.c_double), _c.POINTER(_u64), _c.POINTER(_u64), _sz]),
     "pperm_error_estimate": (_int, [_vp, _c.POINTER(_c.c_double), _c.POINTER(_c.c_double)]),
     "pperm_sequence_stats": (_int, [_vp, _c.POINTER(SeqStats), _sz]),
@@ -89,6 +96,7 @@ SIGNATURES = {
     "pperm_server_info": (_int, [_vp, _u64, _c.POINTER(JobInfo)]),
     "pperm_server_result": (_int, [_vp, _u64, _c.POINTER(_c.c_double), _c.POINTER(_u64), _sz]),
     "pperm_server_release": (_int, [_vp, _u64]),
+    "pperm_server_set_slice": (_int, [_vp, _u32]),
     "pperm_server_counts": (_int, [_vp, _c.POINTER(_u32), _c.POINTER(_u32), _c.POINTER(_u64)]),
     "pperm_server_destroy": (_int, [_vp]),
     "pperm_pool_script": (_c.c_int64, [_u64, _c.POINTER(_c.c_int64), _sz, _c.POINTER(_c.c_int64)]),

@@ -167,6 +167,24 @@ int check_device_errors(pperm_ctx* x) {
     return x->sticky_error;
 }
 
+// The relative-error estimate of the group sums (all groups nonzero): group
+// averages relative to the largest exponent, g_k = ldexp(m_k / C_k, e_k -
+// e_max), their mean and sample variance summed in group order, and
+// sqrt(var) / (4 mean).  Only correctly rounded operations, in a fixed order,
+// so host, device and oracle take the same stop decisions.
+double group_rel_err(const SumRec* sum, const uint64_t* tours, int e_top) {
+    double g[GROUPS];
+    double total = 0.0;
+    for (uint32_t k = 0; k < GROUPS; ++k) {
+        g[k] = ldexp(sum[k].m / (double)tours[k], sum[k].e - e_top);
+        total += g[k];
+    }
+    const double mean = total / GROUPS;
+    double ss = 0.0;
+    for (uint32_t k = 0; k < GROUPS; ++k) ss += (g[k] - mean) * (g[k] - mean);
+    return sqrt(ss / (GROUPS - 1)) / (4.0 * mean);
+}
+
 }  // namespace
 
 extern "C" {
@@ -638,8 +656,8 @@ uint32_t pow2_at_least(uint32_t n) {
 // Workspace of a job: the common part, then per problem its schedule, the
 // per-epoch copies of its pooled sums and its merge-tree flags.
 struct JobLayout {
-    uint64_t probs, state, order, counters, total;
-    std::vector<uint64_t> sched, gver, flags;
+    uint64_t probs, state, order, counters, results, total;
+    std::vector<uint64_t> sched, gver, flags, stage, stage_m;
 };
 
 void job_layout(pperm_ctx* const* ctxs, const uint32_t* epochs, size_t count, JobLayout* L) {
@@ -653,14 +671,19 @@ void job_layout(pperm_ctx* const* ctxs, const uint32_t* epochs, size_t count, Jo
     L->state = take(count * sizeof(JobState));
     L->order = take(count * 4);
     L->counters = take(JOB_COUNTER_WORDS * 4);
+    L->results = take(count * 4 * 4);
     L->sched.assign(count, 0);
     L->gver.assign(count, 0);
     L->flags.assign(count, 0);
+    L->stage.assign(count, 0);
+    L->stage_m.assign(count, 0);
     for (size_t i = 0; i < count; ++i) {
         const pperm_ctx* x = ctxs[i];
         L->sched[i] = take((uint64_t)epochs[i] * 4);
         L->gver[i] = take((uint64_t)epochs[i] * (x->lay.row + JOB_GAP) * sizeof(SumRec));
         L->flags[i] = take((uint64_t)pow2_at_least(x->cfg.n_sequences) * 4);
+        L->stage[i] = take((uint64_t)x->cfg.n_sequences * sizeof(SumRec));
+        L->stage_m[i] = take((uint64_t)x->cfg.n_sequences * 4);
     }
     L->total = off;
 }
@@ -703,12 +726,22 @@ int pperm_job_workspace_bytes(pperm_ctx* const* ctxs, const uint32_t* epochs, si
     return PPERM_OK;
 }
 
-int pperm_run_job(pperm_ctx* const* ctxs, const uint32_t* const* schedules, const uint32_t* epochs,
-                  size_t count, void* d_workspace, size_t bytes, void* hip_stream) {
+namespace {
+
+// The chained launch; limits (per problem, may be NULL) switch the on-device
+// stop rule on, slice_us (0: none) closes the starting of epochs after that
+// long.  Host counters of the contexts are left to the callers.
+int run_job_impl(pperm_ctx* const* ctxs, const uint32_t* const* schedules, const uint32_t* epochs,
+                 size_t count, void* d_workspace, size_t bytes, void* hip_stream,
+                 const pperm_job_limits* limits, uint32_t slice_us, JobLayout* Lout) {
     if (!schedules || !d_workspace) return PPERM_EINVAL;
     int device = -1;
     int rc = job_validate(ctxs, schedules, epochs, count, &device);
     if (rc) return rc;
+    if (limits)
+        for (size_t i = 0; i < count; ++i)
+            if (limits[i].target_rel_err > 0.0 && !(ctxs[i]->cfg.flags & PPERM_FLAG_GROUP_STATS))
+                return PPERM_EINVAL;
     JobLayout L;
     job_layout(ctxs, epochs, count, &L);
     if (bytes < L.total || ((uintptr_t)d_workspace & 255u)) return PPERM_EINVAL;
@@ -786,6 +819,14 @@ int pperm_run_job(pperm_ctx* const* ctxs, const uint32_t* const* schedules, cons
         J.levels = log2u(J.p2);
         J.cls = pcls[i];
         J.lds = lds_of(x);
+        J.result = reinterpret_cast<uint32_t*>(ws + L.results) + 4 * i;
+        if (limits) {
+            J.stage = reinterpret_cast<SumRec*>(ws + L.stage[i]);
+            J.stage_m = reinterpret_cast<uint32_t*>(ws + L.stage_m[i]);
+            J.gsum = at<SumRec>(x, x->lay.groups);
+            J.target = limits[i].target_rel_err;
+            J.cap = limits[i].tour_cap;
+        }
         // chains within a factor 2, 4, 8 of the longest get priorities 3, 2, 1
         const double top = *std::max_element(chain.begin(), chain.end());
         J.prio = (top > 0 && chain[i] * 2 >= top) ? 3u : (chain[i] * 4 >= top) ? 2u : (chain[i] * 8 >= top) ? 1u : 0u;
@@ -829,6 +870,7 @@ int pperm_run_job(pperm_ctx* const* ctxs, const uint32_t* const* schedules, cons
         a.start = start[c];
         a.cls = c;
         a.need = need[c];
+        a.slice_ticks = (uint64_t)slice_us * 100u;   // the 100 MHz real-time clock
         HIP_TRY(hipStreamWaitEvent(ds->s[c], ds->fork, 0));
         HIP_TRY(launch_job(a, (uint32_t)wgs, cls_lds[c], ds->s[c]));
         HIP_TRY(hipEventRecord(ds->join[c], ds->s[c]));
@@ -840,9 +882,50 @@ int pperm_run_job(pperm_ctx* const* ctxs, const uint32_t* const* schedules, cons
         if (!epochs[i]) continue;
         HIP_TRY(launch_fill_zero(x->ws + x->lay.L, (size_t)x->cfg.n_sequences * x->lay.row * sizeof(SumRec),
                                  stream));
+    }
+    if (Lout) *Lout = L;
+    return PPERM_OK;
+}
+
+}  // namespace
+
+int pperm_run_job(pperm_ctx* const* ctxs, const uint32_t* const* schedules, const uint32_t* epochs,
+                  size_t count, void* d_workspace, size_t bytes, void* hip_stream) {
+    int rc = run_job_impl(ctxs, schedules, epochs, count, d_workspace, bytes, hip_stream, nullptr, 0, nullptr);
+    if (rc) return rc;
+    for (size_t i = 0; i < count; ++i) {
         uint64_t total = 0;
         for (uint32_t e = 0; e < epochs[i]; ++e) total += schedules[i][e];
-        x->merged_tours += (uint64_t)x->cfg.n_sequences * total;
+        ctxs[i]->merged_tours += (uint64_t)ctxs[i]->cfg.n_sequences * total;
+    }
+    return PPERM_OK;
+}
+
+int pperm_run_job_sliced(pperm_ctx* const* ctxs, const uint32_t* const* schedules, const uint32_t* epochs,
+                         size_t count, void* d_workspace, size_t bytes, void* hip_stream,
+                         const pperm_job_limits* limits, uint32_t slice_us, uint32_t* epochs_done,
+                         uint32_t* stop, double* rel_err) {
+    if (!epochs_done) return PPERM_EINVAL;
+    JobLayout L;
+    int rc = run_job_impl(ctxs, schedules, epochs, count, d_workspace, bytes, hip_stream, limits, slice_us, &L);
+    if (rc) return rc;
+    std::vector<uint32_t> res(count * 4, 0);
+    HIP_TRY(hipMemcpyAsync(res.data(), (unsigned char*)d_workspace + L.results, res.size() * 4,
+                           hipMemcpyDeviceToHost, (hipStream_t)hip_stream));
+    HIP_TRY(hipStreamSynchronize((hipStream_t)hip_stream));
+    for (size_t i = 0; i < count; ++i) {
+        const uint32_t done = res[4 * i];
+        uint64_t total = 0;
+        for (uint32_t e = 0; e < done && e < epochs[i]; ++e) total += schedules[i][e];
+        ctxs[i]->merged_tours += (uint64_t)ctxs[i]->cfg.n_sequences * total;
+        epochs_done[i] = done;
+        if (stop) stop[i] = res[4 * i + 1];
+        if (rel_err) {
+            const uint64_t bits = (uint64_t)res[4 * i + 2] | ((uint64_t)res[4 * i + 3] << 32);
+            double r;
+            memcpy(&r, &bits, 8);
+            rel_err[i] = done ? r : INFINITY;
+        }
     }
     return PPERM_OK;
 }
@@ -918,33 +1001,17 @@ int pperm_error_estimate(pperm_ctx* x, double* rel_err, double* log_groups) {
                            hipMemcpyDeviceToHost, x->stream));
     HIP_TRY(hipStreamSynchronize(x->stream));
     const double ln2 = 0.69314718055994530942;
-    double lg[GROUPS];
     bool defined = true;
-    double top = -INFINITY;
+    int e_top = INT32_MIN;
     for (uint32_t k = 0; k < GROUPS; ++k) {
-        if (g.tours[k] == 0 || g.sum[k].m == 0.0) {
-            defined = false;
-            lg[k] = -INFINITY;
-        } else {
-            lg[k] = log(g.sum[k].m) + g.sum[k].e * ln2 - log((double)g.tours[k]);
-        }
-        if (lg[k] > top) top = lg[k];
-        if (log_groups) log_groups[k] = lg[k];
+        if (g.tours[k] == 0 || g.sum[k].m == 0.0) defined = false;
+        else if (g.sum[k].e > e_top) e_top = g.sum[k].e;
+        if (log_groups)
+            log_groups[k] = (g.tours[k] == 0 || g.sum[k].m == 0.0)
+                                ? -INFINITY
+                                : log(g.sum[k].m) + g.sum[k].e * ln2 - log((double)g.tours[k]);
     }
-    if (!defined) {
-        *rel_err = INFINITY;
-        return PPERM_OK;
-    }
-    // scale-free: the groups relative to the largest one
-    double xs[GROUPS], mean = 0.0;
-    for (uint32_t k = 0; k < GROUPS; ++k) {
-        xs[k] = exp(lg[k] - top);
-        mean += xs[k];
-    }
-    mean /= GROUPS;
-    double ss = 0.0;
-    for (uint32_t k = 0; k < GROUPS; ++k) ss += (xs[k] - mean) * (xs[k] - mean);
-    *rel_err = sqrt(ss / (GROUPS - 1)) / (4.0 * mean);
+    *rel_err = defined ? group_rel_err(g.sum, g.tours, e_top) : INFINITY;
     return PPERM_OK;
 }
 

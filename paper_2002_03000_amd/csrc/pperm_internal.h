@@ -141,6 +141,13 @@ struct JobProblem {
     uint32_t lds;             // LDS bytes its walks need
     uint32_t prio;            // issue priority 0..3 of its waves (longest chains highest)
     uint32_t pad;
+    // stop rule (evaluated after every merge; stage == nullptr: none)
+    SumRec* stage;            // [N] each sequence's record at n_max in the open epoch
+    uint32_t* stage_m;        // [N] its tours in the open epoch
+    SumRec* gsum;             // the context's 16 group sums, then 16 u64 group tours
+    uint32_t* result;         // [4]: epochs done, stop reason (1 target, 2 cap), rel. error (2 words)
+    double target;            // relative-error target, 0: none
+    uint64_t cap;             // stop once the pooled tours M reach this, 0: none
 };
 
 // Per-problem scheduling word: (epoch << 32) | sequences claimed in it; and
@@ -151,7 +158,7 @@ struct JobState {
     uint32_t pad;
 };
 
-enum : uint32_t { JOB_FINISHED0 = 0, JOB_PROGRESS = 4, JOB_ERROR = 5, JOB_COUNTER_WORDS = 8 };
+enum : uint32_t { JOB_FINISHED0 = 0, JOB_PROGRESS = 4, JOB_ERROR = 5, JOB_CLOCK = 8, JOB_COUNTER_WORDS = 16 };
 // records between consecutive per-epoch copies of the pooled sums (256 bytes)
 constexpr uint32_t JOB_GAP = 16;
 
@@ -164,6 +171,7 @@ struct JobArgs {
     uint32_t start;           // first position of `order` this launch's waves may take
     uint32_t cls;             // this launch's LDS class
     uint32_t need;            // problems of classes <= cls
+    uint64_t slice_ticks;     // 100 MHz ticks after which no epoch starts, 0: none
 };
 
 hipError_t launch_job(const JobArgs& a, uint32_t workgroups, uint32_t lds_bytes, hipStream_t s);

@@ -1009,11 +1009,11 @@ __device__ __forceinline__ uint32_t job_finished(const JobArgs& A) {
 
 // Lane 0 tries to claim the next sequence of problem pi's open epoch.
 __device__ __forceinline__ bool job_claim(const JobArgs& A, uint32_t pi, uint32_t epochs, uint32_t N,
-                                          uint32_t& e, uint32_t& s) {
+                                          bool closed, uint32_t& e, uint32_t& s) {
     unsigned long long w = __hip_atomic_load(&A.state[pi].word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (int attempt = 0; attempt < 8; ++attempt) {
         const uint32_t ee = (uint32_t)(w >> 32), cc = (uint32_t)w;
-        if (ee >= epochs || cc >= N) return false;
+        if (ee >= epochs || cc >= N || (closed && cc == 0u && ee > 0u)) return false;
         if (__hip_atomic_compare_exchange_strong(&A.state[pi].word, &w, w + 1ull, __ATOMIC_ACQUIRE,
                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
             e = ee;
@@ -1036,6 +1036,11 @@ __device__ void job_merge(const JobArgs& A, const JobProblem& J, const ProblemDe
     if (lane == 0) {
         __hip_atomic_fetch_add(&A.state[pi].msum, tours_run, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         P.m[s] = 0u;
+        if (J.stage != nullptr) {
+            // what the group sums of the stop rule need, before the tree overwrites the row
+            store_global(J.stage + s, Ls[P.n_max]);
+            J.stage_m[s] = tours_run;
+        }
     }
     uint32_t l = 0, i = s;
     for (;;) {
@@ -1084,16 +1089,81 @@ __device__ void job_merge(const JobArgs& A, const JobProblem& J, const ProblemDe
         store_global(Gnext + n, r);
         store_global(Gctx + n, r);
     }
+    // the stop rule's group sums: lane k < 16 folds group k (sequences k, k + 16,
+    // ... in order) into the context's running group sum and tour count
+    double rel = __builtin_inf();
+    if (J.stage != nullptr) {
+        double gm = 0.0;
+        int ge = 0;
+        uint64_t gt = 0;
+        if ((uint32_t)lane < GROUPS) {
+            XF acc = {0.0, 0};
+            uint64_t t = 0;
+            for (uint32_t q = (uint32_t)lane; q < J.N; q += GROUPS) {
+                acc = xf_add(acc, xf_of(load_global(J.stage + q)));
+                t += J.stage_m[q];
+            }
+            const XF g = xf_add(xf_of(load_global(J.gsum + lane)), acc);
+            uint64_t* gtours = reinterpret_cast<uint64_t*>(J.gsum + GROUPS);
+            gt = gtours[lane] + t;
+            SumRec r;
+            r.m = g.m;
+            r.e = g.e;
+            r.h = 0u;
+            store_global(J.gsum + lane, r);
+            gtours[lane] = gt;
+            gm = g.m;
+            ge = g.e;
+        }
+        // the same fixed sequence of operations as the host's group_rel_err
+        bool defined = true;
+        int e_top = -2147483647 - 1;
+        for (uint32_t k = 0; k < GROUPS; ++k) {
+            const double mk = __hiloint2double((int)lane_value((uint32_t)__double2hiint(gm), k),
+                                               (int)lane_value((uint32_t)__double2loint(gm), k));
+            const int ek = (int)lane_value((uint32_t)ge, k);
+            const uint64_t tk = lane_value(gt, k);
+            if (tk == 0 || mk == 0.0) defined = false;
+            else if (ek > e_top) e_top = ek;
+        }
+        if (defined) {
+            double g[GROUPS];
+            double total = 0.0;
+            for (uint32_t k = 0; k < GROUPS; ++k) {
+                const double mk = __hiloint2double((int)lane_value((uint32_t)__double2hiint(gm), k),
+                                                   (int)lane_value((uint32_t)__double2loint(gm), k));
+                const int ek = (int)lane_value((uint32_t)ge, k);
+                const uint64_t tk = lane_value(gt, k);
+                g[k] = ldexp(mk / (double)tk, ek - e_top);
+                total += g[k];
+            }
+            const double mean = total / GROUPS;
+            double ss = 0.0;
+            for (uint32_t k = 0; k < GROUPS; ++k) ss += (g[k] - mean) * (g[k] - mean);
+            rel = __builtin_sqrt(ss / (GROUPS - 1)) / (4.0 * mean);
+        }
+    }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     if (lane == 0) {
         const uint32_t msum = __hip_atomic_exchange(&A.state[pi].msum, 0u, __ATOMIC_ACQ_REL,
                                                     __HIP_MEMORY_SCOPE_AGENT);
         uint64_t* MG = const_cast<uint64_t*>(P.MG);
-        MG[0] += msum;
+        const uint64_t M = MG[0] + msum;
+        MG[0] = M;
+        uint32_t stop = 0u;
+        if (J.stage != nullptr && J.target > 0.0 && rel <= J.target) stop = 1u;
+        else if (J.cap != 0u && M >= J.cap) stop = 2u;
+        if (J.result != nullptr) {
+            J.result[0] = e + 1u;
+            J.result[1] = stop;
+            J.result[2] = (uint32_t)__double2loint(rel);
+            J.result[3] = (uint32_t)__double2hiint(rel);
+        }
+        const bool last = stop != 0u || e + 1u == J.epochs;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __hip_atomic_store(&A.state[pi].word, (unsigned long long)(e + 1u) << 32, __ATOMIC_RELEASE,
-                           __HIP_MEMORY_SCOPE_AGENT);
-        if (e + 1u == J.epochs)
+        __hip_atomic_store(&A.state[pi].word, (unsigned long long)(last ? J.epochs : e + 1u) << 32,
+                           __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (last)
             __hip_atomic_fetch_add(&A.counters[JOB_FINISHED0 + J.cls], 1u, __ATOMIC_RELEASE,
                                    __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -1104,7 +1174,21 @@ __global__ void __launch_bounds__(64) job_kernel(JobArgs A) {
     const int lane = (int)threadIdx.x;
     uint64_t idle_since = __builtin_amdgcn_s_memrealtime();
     uint32_t seen_progress = 0u;
+    // the slice's clock starts with the first wave to look at it
+    unsigned long long* clock0 = reinterpret_cast<unsigned long long*>(A.counters + JOB_CLOCK);
+    uint64_t start = 0;
+    if (lane == 0) {
+        unsigned long long zero = 0ull;
+        const unsigned long long now0 = __builtin_amdgcn_s_memrealtime();
+        __hip_atomic_compare_exchange_strong(clock0, &zero, now0, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+        start = __hip_atomic_load(clock0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    start = lane_value(start, 0u);
     for (;;) {
+        // past the slice's end, no epoch after a problem's first starts (the
+        // started ones are finished)
+        const bool closed = A.slice_ticks != 0u && __builtin_amdgcn_s_memrealtime() - start >= A.slice_ticks;
         // ---- claim: the first problem (in priority order) with an open item ----
         bool got = false;
         uint32_t pi = 0u, e = 0u, s = 0u;
@@ -1117,7 +1201,10 @@ __global__ void __launch_bounds__(64) job_kernel(JobArgs A) {
                 const JobProblem& J = A.probs[mine];
                 const unsigned long long w =
                     __hip_atomic_load(&A.state[mine].word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                open = (uint32_t)(w >> 32) < J.epochs && (uint32_t)w < J.N;
+                // (a launch always runs each problem's first epoch, so every
+                // call makes progress however short its slice)
+                open = (uint32_t)(w >> 32) < J.epochs && (uint32_t)w < J.N &&
+                       (!closed || (uint32_t)w > 0u || (uint32_t)(w >> 32) == 0u);
             }
             uint64_t cand = __ballot(open);
             while (cand != 0u && !got) {
@@ -1127,7 +1214,7 @@ __global__ void __launch_bounds__(64) job_kernel(JobArgs A) {
                 uint32_t ok = 0u, ce = 0u, cs = 0u;
                 if (lane == 0) {
                     const JobProblem& J = A.probs[p];
-                    ok = job_claim(A, p, J.epochs, J.N, ce, cs) ? 1u : 0u;
+                    ok = job_claim(A, p, J.epochs, J.N, closed, ce, cs) ? 1u : 0u;
                 }
                 ok = ufirst(__shfl(ok, 0, 64));
                 if (ok) {
@@ -1139,6 +1226,9 @@ __global__ void __launch_bounds__(64) job_kernel(JobArgs A) {
             }
         }
         if (!got) {
+            // past the slice's end nothing new becomes claimable (items are only
+            // used up), so a wave that finds nothing may leave
+            if (closed) break;
             if (job_finished(A) >= A.need) break;
             if (__hip_atomic_load(&A.counters[JOB_ERROR], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
             const uint32_t prog =

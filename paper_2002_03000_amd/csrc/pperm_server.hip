@@ -1,16 +1,18 @@
-// Serving on top of the batched launch: continuous batching of sampling jobs.
+// Serving on top of the chained launch: continuous batching of sampling jobs.
 //
 // Host code only.  The server carves job workspaces out of one caller-owned
 // device pool (first-fit over 256-byte blocks, neighbours coalesced on free),
 // admits queued jobs in arrival order while their workspace and their
-// sequences fit, and advances every active job by one epoch per step with a
-// single pperm_run_batch followed by each job's merge.  Between steps a job's
-// resident state is its context (pooled sums, group sums, counters); a job that
-// meets its stop rule after a merge is retired, its estimates are copied to the
-// host and its pool block is returned.
+// sequences fit, and advances every active job by one time slice per step: one
+// pperm_run_job_sliced call in which each job runs its next epochs at its own
+// pace, with its stop rule evaluated on the device after every merge.  Between
+// steps a job's resident state is its context (pooled sums, group sums,
+// counters); a job that has met its stop rule is retired, its estimates are
+// copied to the host and its pool block is returned.
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <deque>
 #include <iterator>
 #include <map>
@@ -24,6 +26,7 @@
 namespace {
 
 constexpr uint64_t kBlock = 256;
+constexpr uint32_t kSliceEpochs = 64;   // most epochs of one job per step
 
 uint64_t round_block(uint64_t x) { return (x + kBlock - 1) / kBlock * kBlock; }
 
@@ -120,8 +123,9 @@ struct pperm_server {
     Pool pool{0};
     uint32_t max_seq = 0;
     hipStream_t stream = nullptr;
-    unsigned char* batch_ws = nullptr;
-    size_t batch_bytes = 0;
+    unsigned char* scratch = nullptr;   // workspace of the chained launches
+    size_t scratch_bytes = 0;
+    uint32_t slice_us = 100000;
     uint64_t next_id = 1;
     uint64_t active_seq = 0;
     std::deque<Job*> queue;
@@ -189,14 +193,14 @@ int pperm_server_create(void* d_pool, size_t pool_bytes, uint32_t max_active_seq
     S->pool = Pool(pool_bytes);
     S->max_seq = max_active_sequences;
     S->stream = (hipStream_t)hip_stream;
-    // scratch of the batched launch: at most one entry per active sequence
-    pperm_batch_workspace_bytes(max_active_sequences, &S->batch_bytes);
-    const int64_t off = S->pool.alloc(S->batch_bytes);
+    // an eighth of the pool (at least 64 KiB) for the chained launches
+    S->scratch_bytes = std::max<size_t>(pool_bytes / 8 / kBlock * kBlock, 65536);
+    const int64_t off = S->pool.alloc(S->scratch_bytes);
     if (off < 0) {
         delete S;
         return PPERM_EINVAL;
     }
-    S->batch_ws = S->pool_base + off;
+    S->scratch = S->pool_base + off;
     *out = S;
     return PPERM_OK;
 }
@@ -206,6 +210,7 @@ int pperm_server_submit(pperm_server* S, const pperm_job* job, uint64_t* id) {
     if (job->struct_size != sizeof(pperm_job)) return PPERM_EINVAL;
     if (job->tours_per_epoch == 0 || job->tour_cap == 0 || job->n_sequences > S->max_seq)
         return PPERM_EINVAL;
+    if (job->mode == PPERM_INDEPENDENT) return PPERM_EINVAL;   // chained launches pool the sums
     if (!(job->target_rel_err >= 0.0)) return PPERM_EINVAL;
     // the pooled tour count stays below 2^32: the job stops at the first merge
     // with M >= tour_cap, so M < tour_cap + N * T
@@ -226,7 +231,7 @@ int pperm_server_submit(pperm_server* S, const pperm_job* job, uint64_t* id) {
     j->cfg.flags = PPERM_FLAG_GROUP_STATS;
     size_t bytes = 0;
     int rc = pperm_workspace_bytes(&j->cfg, &bytes);
-    if (rc == PPERM_OK && round_block(bytes) + round_block(S->batch_bytes) > S->pool.capacity())
+    if (rc == PPERM_OK && round_block(bytes) + S->scratch_bytes > S->pool.capacity())
         rc = PPERM_EINVAL;
     if (rc) {
         delete j;
@@ -275,58 +280,70 @@ int pperm_server_step(pperm_server* S, uint64_t* finished, size_t cap, size_t* n
         return PPERM_OK;
     }
 
-    // one epoch of every active job in one batched launch, then the merges
-    std::vector<pperm_ctx*> ctxs;
-    std::vector<uint32_t> tours;
-    ctxs.reserve(S->active.size());
-    tours.reserve(S->active.size());
-    for (Job* j : S->active) {
-        j->running = epoch_tours(j->spec, j->info.epochs);
-        ctxs.push_back(j->ctx);
-        tours.push_back(j->running);
-    }
-    int rc = pperm_run_batch(ctxs.data(), ctxs.size(), tours.data(), S->batch_ws, S->batch_bytes,
-                             S->stream);
-    if (rc) return rc;
-    for (Job* j : S->active) {
-        rc = pperm_merge_epoch(j->ctx);
+    // the next epochs of every active job (up to its tour cap, at most
+    // kSliceEpochs; fewer while the launch's workspace does not fit)
+    const size_t na = S->active.size();
+    std::vector<pperm_ctx*> ctxs(na);
+    std::vector<std::vector<uint32_t>> sched(na);
+    std::vector<const uint32_t*> sp(na);
+    std::vector<uint32_t> ep(na), done(na), stop(na);
+    std::vector<double> rel(na);
+    std::vector<pperm_job_limits> lim(na);
+    size_t need = 0;
+    for (uint32_t limit = kSliceEpochs;; limit = std::max<uint32_t>(1u, limit / 2)) {
+        for (size_t i = 0; i < na; ++i) {
+            Job* j = S->active[i];
+            ctxs[i] = j->ctx;
+            sched[i].clear();
+            uint64_t M = j->info.tours;
+            while (sched[i].size() < limit && M < j->spec.tour_cap) {
+                const uint32_t T = epoch_tours(j->spec, j->info.epochs + (uint32_t)sched[i].size());
+                sched[i].push_back(T);
+                M += (uint64_t)j->cfg.n_sequences * T;
+            }
+            ep[i] = (uint32_t)sched[i].size();
+            sp[i] = sched[i].data();
+            lim[i].target_rel_err = j->spec.target_rel_err;
+            lim[i].tour_cap = j->spec.tour_cap;
+        }
+        int rc = pperm_job_workspace_bytes(ctxs.data(), ep.data(), na, &need);
         if (rc) return rc;
+        if (need <= S->scratch_bytes) break;
+        if (limit == 1u) return PPERM_ENOMEM;
     }
-    const hipError_t e = hipStreamSynchronize(S->stream);
-    if (e != hipSuccess) return PPERM_EDEVICE;
+    int rc = pperm_run_job_sliced(ctxs.data(), sp.data(), ep.data(), na, S->scratch, S->scratch_bytes, S->stream,
+                                  lim.data(), S->slice_us, done.data(), stop.data(), rel.data());
+    if (rc) return rc;
 
-    // stop rules
+    // progress, stop rules, retirement
     std::vector<Job*> still;
-    still.reserve(S->active.size());
-    for (Job* j : S->active) {
-        j->info.epochs += 1;
-        j->info.tours += (uint64_t)j->cfg.n_sequences * j->running;
+    still.reserve(na);
+    for (size_t i = 0; i < na; ++i) {
+        Job* j = S->active[i];
+        for (uint32_t e = 0; e < done[i]; ++e) j->info.tours += (uint64_t)j->cfg.n_sequences * sched[i][e];
+        j->info.epochs += done[i];
+        if (done[i] && j->spec.target_rel_err > 0.0) j->info.rel_err = rel[i];
         rc = pperm_sync(j->ctx);
         if (rc == PPERM_EDEVICE) return rc;
-        uint32_t stop = 0;
-        if (rc == PPERM_OK) {
-            if (j->spec.target_rel_err > 0.0) {
-                double rel = INFINITY;
-                rc = pperm_error_estimate(j->ctx, &rel, nullptr);
-                if (rc == PPERM_EDEVICE) return rc;
-                j->info.rel_err = rel;
-                if (rc == PPERM_OK && rel <= j->spec.target_rel_err) stop = 1;
-            }
-            if (!stop && j->info.tours >= j->spec.tour_cap) stop = 2;
-        }
-        if (rc == PPERM_OK && !stop) {
+        if (rc == PPERM_OK && stop[i] == 0u) {
             still.push_back(j);
             continue;
         }
         if (rc == PPERM_OK) rc = collect(j);
         if (rc == PPERM_EDEVICE) return rc;
-        j->info.stop = stop;
+        j->info.stop = stop[i];
         S->active_seq -= j->cfg.n_sequences;
         retire(S, j, rc == PPERM_OK ? PPERM_JOB_DONE : PPERM_JOB_FAILED, rc);
         report(j);
     }
     S->active.swap(still);
     *n_finished = nf;
+    return PPERM_OK;
+}
+
+int pperm_server_set_slice(pperm_server* S, uint32_t slice_us) {
+    if (!S || slice_us == 0) return PPERM_EINVAL;
+    S->slice_us = slice_us;
     return PPERM_OK;
 }
 

@@ -206,6 +206,35 @@ def run_job(problems, schedules, stream=None):
     return ws
 
 
+def run_job_sliced(problems, schedules, limits=None, slice_us=0, stream=None):
+    """run_job with per-problem stop rules (limits[i] = (target_rel_err, tour_cap))
+    evaluated on the device after every merge, and a time slice after which no
+    epoch starts.  Synchronises; returns (epochs_done, stop, rel_err) arrays."""
+    lib = _abi.load()
+    count = len(problems)
+    device = problems[0].device
+    ctxs = (ctypes.c_void_p * count)(*[p._ctx for p in problems])
+    epochs = (ctypes.c_uint32 * count)(*[len(s) for s in schedules])
+    arrays = [(ctypes.c_uint32 * max(1, len(s)))(*s) for s in schedules]
+    sched = (ctypes.POINTER(ctypes.c_uint32) * count)(*[ctypes.cast(a, ctypes.POINTER(ctypes.c_uint32))
+                                                        for a in arrays])
+    lim = None
+    if limits is not None:
+        lim = (_abi.JobLimits * count)(*[_abi.JobLimits(float(t), int(c)) for t, c in limits])
+    done = (ctypes.c_uint32 * count)()
+    stop = (ctypes.c_uint32 * count)()
+    rel = (ctypes.c_double * count)()
+    nbytes = ctypes.c_size_t()
+    _abi.check(lib.pperm_job_workspace_bytes(ctxs, epochs, count, ctypes.byref(nbytes)), "pperm_job_workspace_bytes")
+    with torch.cuda.device(device):
+        stream = stream if stream is not None else torch.cuda.current_stream(device)
+        ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=device)
+        _abi.check(lib.pperm_run_job_sliced(ctxs, sched, epochs, count, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                            ctypes.c_void_p(stream.cuda_stream), lim, int(slice_us), done, stop,
+                                            rel), "pperm_run_job_sliced")
+    return np.array(done[:], dtype=np.uint32), np.array(stop[:], dtype=np.uint32), np.array(rel[:])
+
+
 def run_schedules(problems, schedules, batch=None):
     """Run each problem through its own epoch schedule (tours per epoch, a merge
     after each), all problems of an epoch index in one batched launch."""
@@ -285,6 +314,9 @@ class Server:
         """Submit a workloads.Problem-like description."""
         return self.submit(p.dim, p.n_max, p.n_sequences, p.seed, p.tours_per_epoch, tour_cap,
                            target_rel_err, mode=p.mode, stream_id=p.stream, warmup=p.warmup)
+
+    def set_slice(self, slice_us):
+        _abi.check(self._lib.pperm_server_set_slice(self._srv, int(slice_us)), "pperm_server_set_slice")
 
     def step(self, cap=4096):
         """One scheduling step; the ids of the jobs it retired."""

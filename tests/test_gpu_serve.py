@@ -36,18 +36,22 @@ def _job_bytes(spec):
     return (nb.value + 255) // 256 * 256
 
 
-def _serve(specs, stream_ids=None, pool_bytes=256 * MB, max_seq=4096):
+def _serve(specs, stream_ids=None, pool_bytes=256 * MB, max_seq=4096, slice_us=None):
     from paper_2002_03000_amd import Server
     srv = Server(pool_bytes, max_seq)
+    if slice_us is not None:
+        srv.set_slice(slice_us)
     if stream_ids is None:
         stream_ids = list(range(len(specs)))
     ids = [srv.submit(d, n, N, sd, T, cap, tgt, stream_id=sid)
            for sid, (d, n, N, sd, T, cap, tgt) in zip(stream_ids, specs)]
     done, steps, peak_active = set(), 0, 0
     while len(done) < len(ids):
-        done.update(srv.step())
+        fin = srv.step()
+        done.update(fin)
         q, a, _ = srv.counts()
-        peak_active = max(peak_active, a)
+        # jobs held at once in this step: still active, or retired by it
+        peak_active = max(peak_active, a + len(fin))
         steps += 1
         assert steps < 10000
     out = []
@@ -103,10 +107,13 @@ def test_served_jobs_same_alone_and_in_the_mix():
     assert 1 < peak < len(specs)
     roomy, peak2 = _serve(specs)
     assert peak2 == len(specs)
+    # a 1 us slice splits every job's epochs over many more steps
+    sliced, _ = _serve(specs, slice_us=1)
     for i, spec in enumerate(specs):
         alone, _ = _serve([spec], stream_ids=[i])
         _same(mixed[i], roomy[i])
         _same(mixed[i], alone[0])
+        _same(mixed[i], sliced[i])
     stops = [m[0]["stop"] for m in mixed]
     assert 1 in stops and 2 in stops, stops
 
@@ -139,3 +146,40 @@ def test_served_jobs_match_oracle_replay():
         fin = np.isfinite(olc)
         assert np.array_equal(fin, np.isfinite(lc))
         np.testing.assert_allclose(lc[fin], olc[fin], rtol=1e-12, atol=0)
+
+
+def test_sliced_chains_with_stop_rules_match_the_oracle():
+    # chained epochs in 1 us slices (so almost every call runs few epochs),
+    # stop rule on the device, against the oracle's epoch-by-epoch replay
+    from paper_2002_03000_amd import ParallelFlatPERM, run_job_sliced
+    specs = [(2, 40, 32, 201, 4, 4000, 0.02), (3, 30, 16, 202, 8, 3000, 0.05), (2, 25, 16, 203, 16, 20000, 0.01)]
+    probs = [ParallelFlatPERM(d, n, N, sd, stream_id=i, group_stats=True) for i, (d, n, N, sd, T, cap, tgt) in enumerate(specs)]
+    scheds = [workloads.Problem(d, n, N, T, 1000, sd).schedule() for (d, n, N, sd, T, cap, tgt) in specs]
+    pos = [0] * len(specs)
+    stopped = [0] * len(specs)
+    calls = 0
+    while not all(stopped):
+        live = [i for i in range(len(specs)) if not stopped[i]]
+        done, stop, rel = run_job_sliced([probs[i] for i in live], [scheds[i][pos[i]:pos[i] + 50] for i in live],
+                                         limits=[(specs[i][6], specs[i][5]) for i in live], slice_us=1)
+        for k, i in enumerate(live):
+            pos[i] += int(done[k])
+            stopped[i] = int(stop[k])
+        calls += 1
+        assert calls < 5000
+    for i, (d, n, N, sd, T, cap, tgt) in enumerate(specs):
+        o = oracle.Oracle(d, n, N, sd, stream=i, group_stats=True)
+        tours, stop_at = 0, None
+        for e, t in enumerate(scheds[i]):
+            o.run_tours(t)
+            o.merge_epoch()
+            tours += N * t
+            if o.error_estimate() <= tgt:
+                stop_at = (e + 1, 1)
+                break
+            if tours >= cap:
+                stop_at = (e + 1, 2)
+                break
+        assert stop_at == (pos[i], stopped[i]), (i, stop_at, pos[i], stopped[i])
+        assert_pooled_equal(probs[i], o, f"sliced problem {i}")
+    print(f"{calls} sliced calls", flush=True)
