@@ -71,18 +71,21 @@ def lib():
         vp = ctypes.c_void_p
         L.orc_run_epoch.argtypes = [ctypes.POINTER(_Params), ctypes.c_int64, vp, u64p, u64p,
                                     ctypes.c_uint32, vp, u32p, u32p, vp,
-                                    i64p, ctypes.c_int64, ctypes.c_int]
+                                    i64p, ctypes.c_int64, ctypes.c_int, vp]
         L.orc_run_epoch.restype = ctypes.c_int
         L.orc_merge.argtypes = [ctypes.POINTER(_Params), ctypes.c_int64, vp, u32p, u32p,
-                                vp, u64p, u64p]
+                                vp, u64p, u64p, vp, vp]
+        L.orc_observable_r2.argtypes = [ctypes.c_int64, vp, vp, dblp]
         L.orc_group_sums.argtypes = [ctypes.POINTER(_Params), ctypes.c_int64, vp, u32p, vp, u64p]
         L.orc_log_estimates.argtypes = [ctypes.c_int64, vp, ctypes.c_uint64, dblp]
         L.orc_plain_recursive.argtypes = [ctypes.POINTER(_Params), ctypes.c_uint32, vp, u32p]
         L.orc_plain_recursive.restype = ctypes.c_int
-        L.orc_forced_enumerate.argtypes = [ctypes.c_int, ctypes.c_int64, u64p, u64p]
+        L.orc_forced_enumerate.argtypes = [ctypes.c_int, ctypes.c_int64, u64p, u64p, u64p]
         L.orc_forced_enumerate.restype = ctypes.c_int
         L.saw_count.argtypes = [ctypes.c_int, ctypes.c_int, u64p]
         L.saw_count.restype = ctypes.c_int
+        L.saw_count_r2.argtypes = [ctypes.c_int, ctypes.c_int, u64p, u64p]
+        L.saw_count_r2.restype = ctypes.c_int
         _LIB = L
     return _LIB
 
@@ -140,13 +143,25 @@ def saw_counts(dim, n_max):
 def forced_enumerate(dim, n_max):
     """Drive the oracle's scan and weight update over every chain.
 
-    Returns (count[n], bad) where count[n] is the number of chains of length n
-    and bad counts chains whose weight differs from the exact product of a_+."""
+    Returns (count[n], bad, r2sum[n]) where count[n] is the number of chains of
+    length n, bad counts chains whose weight differs from the exact product of
+    a_+, and r2sum[n] sums the chains' squared end-to-end distances."""
     cnt = np.zeros(n_max + 1, dtype=np.uint64)
     bad = np.zeros(1, dtype=np.uint64)
-    if lib().orc_forced_enumerate(dim, n_max, _ptr(cnt, ctypes.c_uint64), _ptr(bad, ctypes.c_uint64)) != 0:
+    r2 = np.zeros(n_max + 1, dtype=np.uint64)
+    if lib().orc_forced_enumerate(dim, n_max, _ptr(cnt, ctypes.c_uint64), _ptr(bad, ctypes.c_uint64),
+                                  _ptr(r2, ctypes.c_uint64)) != 0:
         raise RuntimeError("forced_enumerate failed")
-    return cnt, int(bad[0])
+    return cnt, int(bad[0]), r2
+
+
+def saw_counts_r2(dim, n_max):
+    """Exact c_n and the exact sum of R^2 over the c_n walks, by brute force."""
+    out = np.zeros(n_max + 1, dtype=np.uint64)
+    r2 = np.zeros(n_max + 1, dtype=np.uint64)
+    if lib().saw_count_r2(dim, n_max, _ptr(out, ctypes.c_uint64), _ptr(r2, ctypes.c_uint64)) != 0:
+        raise RuntimeError("saw_count_r2 failed")
+    return out, r2
 
 
 def set_selftest(ops, xyz, max_items):
@@ -172,7 +187,7 @@ class Oracle:
     """Parallel flatPERM state and its epoch schedule (run / merge calls)."""
 
     def __init__(self, dim, n_max, n_sequences, seed, mode=MODE_SHARED, stream=0,
-                 step_cap=0, threads=0, group_stats=False):
+                 step_cap=0, threads=0, group_stats=False, observables=False):
         self.params = _Params(dim, mode, n_max, seed & 0xFFFFFFFFFFFFFFFF, stream, 0, step_cap,
                               n_sequences)
         self.dim, self.n_max, self.N, self.mode = dim, n_max, n_sequences, mode
@@ -189,6 +204,9 @@ class Oracle:
         self.stats = np.zeros(n_sequences, dtype=STATS_DTYPE)
         lib().orc_stats_init(self.stats.ctypes.data, n_sequences)
         self.group_stats = group_stats
+        self.observables = observables
+        self.LR = np.zeros((n_sequences, n1), dtype=XF_DTYPE) if observables else None
+        self.GR = np.zeros(gshape, dtype=XF_DTYPE) if observables else None
         self.gsum = np.zeros(GROUPS, dtype=XF_DTYPE)
         self.gtours = np.zeros(GROUPS, dtype=np.uint64)
 
@@ -202,7 +220,8 @@ class Oracle:
                                  _ptr(self.MG, ctypes.c_uint64), _ptr(self.t, ctypes.c_uint64),
                                  tours, self.L.ctypes.data, _ptr(self.H, ctypes.c_uint32),
                                  _ptr(self.m, ctypes.c_uint32), self.stats.ctypes.data,
-                                 idp, nid, self.threads)
+                                 idp, nid, self.threads,
+                                 self.LR.ctypes.data if self.observables else None)
         return bool(rc)
 
     def merge_epoch(self):
@@ -213,7 +232,9 @@ class Oracle:
         lib().orc_merge(ctypes.byref(self.params), self.N, self.L.ctypes.data,
                         _ptr(self.H, ctypes.c_uint32), _ptr(self.m, ctypes.c_uint32),
                         self.G.ctypes.data, _ptr(self.HG, ctypes.c_uint64),
-                        _ptr(self.MG, ctypes.c_uint64))
+                        _ptr(self.MG, ctypes.c_uint64),
+                        self.LR.ctypes.data if self.observables else None,
+                        self.GR.ctypes.data if self.observables else None)
 
     def log_estimates(self):
         """log c_n: the pooled average (shared mode) or, in independent mode, the
@@ -247,6 +268,12 @@ class Oracle:
         for x in g:
             ss += (x - mean) * (x - mean)
         return math.sqrt(ss / (GROUPS - 1)) / (4.0 * mean)
+
+    def observable_r2(self):
+        """<R^2_n> by the ratio estimator of eqn (42MC) (shared mode), NaN where no sample."""
+        out = np.zeros(self.n_max + 1)
+        lib().orc_observable_r2(self.n_max, self.G.ctypes.data, self.GR.ctypes.data, _ptr(out, ctypes.c_double))
+        return out
 
     def walk_steps(self):
         return int(self.stats["steps"].sum())

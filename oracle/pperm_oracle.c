@@ -400,6 +400,8 @@ static double orc_uniform53(const uint32_t B[4])
 /*   G, MG : the pooled sums this sequence sees (Alg 2: shared by all; Alg 1: */
 /*           the sequence's own; unused for the Rosenbluth mode)             */
 /*   L, H  : this sequence's sums of the current epoch (length n_max + 1)     */
+/*   LR    : this sequence's sums of W * R^2 (squared end-to-end distance),   */
+/*           the numerator of the ratio estimator, eqn (42MC); NULL: none     */
 /*   m     : this sequence's tours in the current epoch                      */
 /*   t     : this sequence's global tour counter                             */
 /* Returns 0, or 1 if the step cap stopped the sequence.                    */
@@ -408,7 +410,7 @@ typedef struct { int64_t n; uint64_t remaining; orc_xf w; } orc_entry;
 
 int orc_run_sequence(const orc_params* P, const orc_xf* G, uint64_t MG,
                      uint32_t s, uint64_t* t, uint32_t tours,
-                     orc_xf* L, uint32_t* H, uint32_t* m, orc_seq_stats* st)
+                     orc_xf* L, uint32_t* H, uint32_t* m, orc_seq_stats* st, orc_xf* LR)
 {
     const int dim = P->dim;
     const int64_t n_max = P->n_max;
@@ -488,6 +490,12 @@ int orc_run_sequence(const orc_params* P, const orc_xf* G, uint64_t MG,
                 /* arrival: record into the running sums (eqn (4)) */
                 L[walk.n] = orc_xf_add(L[walk.n], w);
                 H[walk.n] += 1;
+                if (LR) {
+                    const int64_t q = walk.n;
+                    const double r2 = (double)((int64_t)walk.x[q] * walk.x[q] + (int64_t)walk.y[q] * walk.y[q] +
+                                               (int64_t)walk.z[q] * walk.z[q]);
+                    LR[q] = orc_xf_add(LR[q], orc_xf_mul(w, r2));
+                }
                 if (P->step_cap && steps_this_call >= P->step_cap) { capped = 1; break; }
                 if (walk.n == n_max) {
                     need_backtrack = 1;
@@ -529,7 +537,7 @@ int orc_run_sequence(const orc_params* P, const orc_xf* G, uint64_t MG,
 /* ------------------------------------------------------------------------ */
 int orc_run_epoch(const orc_params* P, int64_t N, const orc_xf* G, const uint64_t* MG,
                   uint64_t* t, uint32_t tours, orc_xf* L, uint32_t* H, uint32_t* m,
-                  orc_seq_stats* stats, const int64_t* ids, int64_t n_ids, int threads)
+                  orc_seq_stats* stats, const int64_t* ids, int64_t n_ids, int threads, orc_xf* LR)
 {
     const int64_t n1 = P->n_max + 1;
     const int64_t count = ids ? n_ids : N;
@@ -546,7 +554,7 @@ int orc_run_epoch(const orc_params* P, int64_t N, const orc_xf* G, const uint64_
         uint64_t Ms = MG ? MG[0] : 0;
         if (P->mode == ORC_MODE_INDEPENDENT) { Gs = G + s * n1; Ms = MG[s]; }
         int rc = orc_run_sequence(&Q, Gs, Ms, (uint32_t)s, &t[s], tours,
-                                  L + s * n1, H + s * n1, &m[s], &stats[s]);
+                                  L + s * n1, H + s * n1, &m[s], &stats[s], LR ? LR + s * n1 : NULL);
         if (rc != 0) any_capped |= 1;
     }
     (void)threads;
@@ -574,7 +582,7 @@ static orc_xf orc_pairwise(const orc_xf* L, int64_t n1, int64_t n, int64_t N,
  * Independent mode: per sequence, G[s][n] += L[s][n] (and the same for HG, MG).
  * Afterwards L, H and m are zero. */
 void orc_merge(const orc_params* P, int64_t N, orc_xf* L, uint32_t* H, uint32_t* m,
-               orc_xf* G, uint64_t* HG, uint64_t* MG)
+               orc_xf* G, uint64_t* HG, uint64_t* MG, orc_xf* LR, orc_xf* GR)
 {
     const int64_t n1 = P->n_max + 1;
     if (P->mode == ORC_MODE_INDEPENDENT) {
@@ -590,6 +598,7 @@ void orc_merge(const orc_params* P, int64_t N, orc_xf* L, uint32_t* H, uint32_t*
         while (P2 < N) P2 <<= 1;
         for (int64_t n = 0; n < n1; ++n) {
             G[n] = orc_xf_add(G[n], orc_pairwise(L, n1, n, N, 0, P2));
+            if (LR && GR) GR[n] = orc_xf_add(GR[n], orc_pairwise(LR, n1, n, N, 0, P2));
             uint64_t h = 0;
             for (int64_t s = 0; s < N; ++s) h += H[s * n1 + n];
             HG[n] += h;
@@ -599,6 +608,7 @@ void orc_merge(const orc_params* P, int64_t N, orc_xf* L, uint32_t* H, uint32_t*
         MG[0] += mm;
     }
     memset(L, 0, sizeof(orc_xf) * (size_t)(N * n1));
+    if (LR) memset(LR, 0, sizeof(orc_xf) * (size_t)(N * n1));
     memset(H, 0, sizeof(uint32_t) * (size_t)(N * n1));
     memset(m, 0, sizeof(uint32_t) * (size_t)N);
 }
@@ -622,6 +632,14 @@ void orc_group_sums(const orc_params* P, int64_t N, const orc_xf* L, const uint3
         gsum[k] = orc_xf_add(gsum[k], acc);
         gtours[k] += tours;
     }
+}
+
+/* Ratio estimator (eqn (42MC)) of the mean squared end-to-end distance:
+ * <R^2>_n = (sum of W R^2) / (sum of W) at each length, NaN where no sample. */
+void orc_observable_r2(int64_t n_max, const orc_xf* G, const orc_xf* GR, double* out)
+{
+    for (int64_t n = 0; n <= n_max; ++n)
+        out[n] = (G[n].m == 0.0) ? NAN : ldexp(GR[n].m / G[n].m, GR[n].e - G[n].e);
 }
 
 /* Estimates (eqn (4)): log c_n = ln G_n.m + G_n.e ln 2 - ln M. */
@@ -724,10 +742,11 @@ int orc_plain_recursive(const orc_params* P, uint32_t tours, orc_xf* L, uint32_t
 /* of the floating-point update, so this checks eqns (1)-(3) chain by chain. */
 /* ------------------------------------------------------------------------ */
 static void orc_force_rec(orc_walk* W, int64_t n_max, orc_xf w, uint64_t prod,
-                          uint64_t* count, uint64_t* bad)
+                          uint64_t* count, uint64_t* bad, uint64_t* r2sum)
 {
     int64_t n = W->n;
     count[n] += 1;
+    r2sum[n] += (uint64_t)((int64_t)W->x[n] * W->x[n] + (int64_t)W->y[n] * W->y[n] + (int64_t)W->z[n] * W->z[n]);
     if (ldexp(w.m, w.e) != (double)prod) bad[0] += 1;
     if (n == n_max) return;
     int a;
@@ -736,18 +755,19 @@ static void orc_force_rec(orc_walk* W, int64_t n_max, orc_xf w, uint64_t prod,
         int dir = orc_nth_free(mask, (unsigned)j);
         orc_xf w2 = orc_xf_mul(w, (double)a);
         orc_walk_push(W, dir);
-        orc_force_rec(W, n_max, w2, prod * (uint64_t)a, count, bad);
+        orc_force_rec(W, n_max, w2, prod * (uint64_t)a, count, bad, r2sum);
         orc_walk_truncate(W, n);
     }
 }
 
-int orc_forced_enumerate(int dim, int64_t n_max, uint64_t* count, uint64_t* bad)
+int orc_forced_enumerate(int dim, int64_t n_max, uint64_t* count, uint64_t* bad, uint64_t* r2sum)
 {
     orc_walk W;
     if (orc_walk_init(&W, dim, n_max)) return -1;
     memset(count, 0, sizeof(uint64_t) * (size_t)(n_max + 1));
+    memset(r2sum, 0, sizeof(uint64_t) * (size_t)(n_max + 1));
     bad[0] = 0;
-    orc_force_rec(&W, n_max, orc_xf_from_double(1.0), 1, count, bad);
+    orc_force_rec(&W, n_max, orc_xf_from_double(1.0), 1, count, bad, r2sum);
     orc_walk_free(&W);
     return 0;
 }

@@ -23,11 +23,27 @@ typedef struct {
     int64_t stride[3];
     uint8_t* grid;
     uint64_t* count;
+    uint64_t* r2;        /* sum over walks of the squared end-to-end distance, or NULL */
+    int64_t origin;
 } saw_ctx;
+
+static uint64_t saw_r2_of(const saw_ctx* c, int64_t pos)
+{
+    /* coordinates from the grid index (each in [0, side), the origin at n_max + 1) */
+    uint64_t r2 = 0;
+    int64_t rest = pos;
+    for (int i = c->dim - 1; i >= 0; --i) {
+        const int64_t coord = rest / c->stride[i] - (c->n_max + 1);
+        rest %= c->stride[i];
+        r2 += (uint64_t)(coord * coord);
+    }
+    return r2;
+}
 
 static void saw_dfs(saw_ctx* c, int64_t pos, int n)
 {
     c->count[n] += 1;
+    if (c->r2) c->r2[n] += saw_r2_of(c, pos);
     if (n == c->n_max) return;
     for (int axis = 0; axis < c->dim; ++axis) {
         for (int sgn = -1; sgn <= 1; sgn += 2) {
@@ -41,8 +57,9 @@ static void saw_dfs(saw_ctx* c, int64_t pos, int n)
     }
 }
 
-/* count[n] = c_n for n = 0..n_max.  Returns 0 on success. */
-int saw_count(int dim, int n_max, uint64_t* count)
+/* count[n] = c_n for n = 0..n_max, and (r2 != NULL) r2[n] = the sum over
+ * those walks of the squared end-to-end distance.  Returns 0 on success. */
+int saw_count_r2(int dim, int n_max, uint64_t* count, uint64_t* r2)
 {
     if (dim < 1 || dim > 3 || n_max < 0) return -1;
     saw_ctx c;
@@ -59,6 +76,12 @@ int saw_count(int dim, int n_max, uint64_t* count)
     uint64_t* half = (uint64_t*)calloc((size_t)n_max + 1, sizeof(uint64_t));
     if (!half) { free(c.grid); return -1; }
     c.count = half;
+    uint64_t* half_r2 = NULL;
+    if (r2) {
+        half_r2 = (uint64_t*)calloc((size_t)n_max + 1, sizeof(uint64_t));
+        if (!half_r2) { free(half); free(c.grid); return -1; }
+    }
+    c.r2 = half_r2;
     int64_t origin = 0;
     for (int i = 0; i < dim; ++i) origin += (int64_t)(n_max + 1) * c.stride[i];
     c.grid[origin] = 1;
@@ -69,8 +92,15 @@ int saw_count(int dim, int n_max, uint64_t* count)
         c.grid[first] = 1;
         saw_dfs(&c, first, 1);
         for (int n = 1; n <= n_max; ++n) count[n] = half[n] * (uint64_t)(2 * dim);
+        /* rotations and reflections keep |end|^2, so the first-step symmetry holds for it too */
+        if (r2)
+            for (int n = 1; n <= n_max; ++n) r2[n] = half_r2[n] * (uint64_t)(2 * dim);
     }
+    if (r2) r2[0] = 0;
+    free(half_r2);
     free(half);
     free(c.grid);
     return 0;
 }
+
+int saw_count(int dim, int n_max, uint64_t* count) { return saw_count_r2(dim, n_max, count, NULL); }

@@ -65,7 +65,7 @@ def test_forced_choice_drive_counts_every_walk_once(dim, n_max):
     # Every chain the sampler's scan admits is a SAW and every SAW is reached
     # exactly once; W(S) equals prod a_+ exactly (eqn (2)), hence
     # sum_S Pr(S) W(S) = #chains = c_n (eqn (3)).
-    cnt, bad = oracle.forced_enumerate(dim, n_max)
+    cnt, bad, _ = oracle.forced_enumerate(dim, n_max)
     assert bad == 0
     assert [int(x) for x in cnt] == [SAW[dim][n] for n in range(n_max + 1)]
 
@@ -387,3 +387,47 @@ def test_group_sums_and_error_estimate_pinned():
     assert abs(o.error_estimate() / ref - 1) < 1e-12
     # an empty group leaves the estimate undefined
     assert oracle.Oracle(2, n_max, 8, 1, group_stats=True).error_estimate() == math.inf
+
+
+@pytest.mark.parametrize("dim,n_max", [(2, 10), (3, 7)])
+def test_r2_of_every_chain_matches_brute_force(dim, n_max):
+    # the endpoint coordinates the oracle's walk carries give the same sum of
+    # R^2 over all walks as an independent grid enumeration
+    cnt, bad, r2 = oracle.forced_enumerate(dim, n_max)
+    c, r2_exact = oracle.saw_counts_r2(dim, n_max)
+    assert np.array_equal(cnt, c) and bad == 0
+    assert np.array_equal(r2, r2_exact)
+    # textbook values: <R^2_1> = 1, <R^2_2> = (4 + 2 (2d - 2)) / (2d - 1)
+    assert r2_exact[1] == c[1]
+    assert r2_exact[2] * (2 * dim - 1) == c[2] * (4 + 2 * (2 * dim - 2))
+
+
+def test_ratio_estimator_exact_at_one_step_and_unbiased():
+    # <R^2_1> = 1 for every sample (all one-step walks have R^2 = 1)
+    n_max = 10
+    c, r2 = oracle.saw_counts_r2(2, n_max)
+    exact = r2.astype(np.float64) / c.astype(np.float64)
+    ests = []
+    for seed in range(64):
+        o = oracle.Oracle(2, n_max, 8, 500 + seed, observables=True)
+        for T in (1, 1, 2, 4, 8):
+            o.run_tours(T)
+            o.merge_epoch()
+        v = o.observable_r2()
+        assert v[1] == 1.0
+        ests.append(v)
+    ests = np.array(ests)
+    mean = ests.mean(axis=0)
+    se = ests.std(axis=0, ddof=1) / np.sqrt(len(ests))
+    for n in range(2, n_max + 1):
+        assert abs(mean[n] - exact[n]) < 4.5 * se[n] + 1e-9, (n, mean[n], exact[n], se[n])
+
+
+def test_observables_do_not_change_the_walks():
+    a = oracle.Oracle(3, 30, 10, 77, observables=True)
+    b = oracle.Oracle(3, 30, 10, 77)
+    for o in (a, b):
+        for T in (1, 1, 2):
+            o.run_tours(T)
+            o.merge_epoch()
+    assert np.array_equal(a.G["m"], b.G["m"]) and np.array_equal(a.stats["digest"], b.stats["digest"])
