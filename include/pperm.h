@@ -66,7 +66,7 @@ typedef struct pperm_config {
     uint32_t step_cap;        /* growth steps per sequence per pperm_run_tours call after
                                  which the sequence stops with PPERM_EOVERFLOW; 0 = the
                                  watchdog default min(2^31, 4096 * tours * (n_max + 1))  */
-    uint32_t flags;           /* 0 or PPERM_FLAG_GROUP_STATS                               */
+    uint32_t flags;           /* PPERM_FLAG_GROUP_STATS | PPERM_FLAG_OBSERVABLES, or 0     */
 } pperm_config;
 
 /* Keep 16 group sums of the weights recorded at n_max (sequence s in group
@@ -74,6 +74,14 @@ typedef struct pperm_config {
  * small kernel to every merge; never changes any other result. */
 #define PPERM_FLAG_GROUP_STATS  1u
 #define PPERM_GROUPS            16u
+
+/* Keep, beside every weight sum, the sum of W * R^2 over the same samples
+ * (R^2: squared end-to-end distance of the walk), merged like the weights, for
+ * the ratio estimator of eqn (42MC) (pperm_observable_r2).  Needs one walk per
+ * wavefront and PPERM_SHARED or PPERM_ROSENBLUTH mode; such contexts run
+ * through pperm_run_tours / pperm_merge_epoch (and their graphs) only.  The
+ * walks themselves, and every other result, are unchanged. */
+#define PPERM_FLAG_OBSERVABLES  2u
 
 /* Per-sequence counters, cumulative over the context's life (10 x uint64 each). */
 typedef struct pperm_seq_stats {
@@ -110,6 +118,8 @@ typedef struct pperm_layout {
     uint32_t row;        /* n1p: records per row of G/HG/L (>= n_max + 1)                */
     uint32_t stack_slots;/* walks that can be in flight at once                           */
     uint64_t groups;     /* 16 records (group sums at n_max) then 16 u64 (group tours)  */
+    uint64_t obs_L;      /* records [N][n1p]: epoch sums of W * R^2 (0: no observables)  */
+    uint64_t obs_G;      /* records [n1p]: pooled sums of W * R^2 (0: no observables)     */
 } pperm_layout;
 
 typedef struct pperm_ctx pperm_ctx;
@@ -230,6 +240,15 @@ int pperm_estimates(pperm_ctx* ctx, double* log_cn, uint64_t* hist, uint64_t* to
  * +inf while a group has no tour or no weight at n_max.  log_groups (16 entries,
  * may be NULL) receives log g_k.  Errors: EINVAL (flag not set), EDEVICE. */
 int pperm_error_estimate(pperm_ctx* ctx, double* rel_err, double* log_groups);
+
+/* Synchronise and read the ratio estimator of eqn (42MC) for O = R^2, the mean
+ * squared end-to-end distance of walks of length n under the uniform
+ * distribution: out[n] = (pooled sum of W * R^2) / (pooled sum of W), from the
+ * merged epochs, NaN where no sample reached n (out[0] = 0).  out: caller-owned
+ * host buffer of len >= n_max + 1 entries.  Errors: EINVAL (no
+ * PPERM_FLAG_OBSERVABLES, short buffer), ESTATE (no merged tour yet), ERANGE /
+ * EOVERFLOW (raised by a kernel since the last check), EDEVICE. */
+int pperm_observable_r2(pperm_ctx* ctx, double* out, size_t len);
 
 /* Synchronise and copy the per-sequence counters into `out` (N entries). */
 int pperm_sequence_stats(pperm_ctx* ctx, pperm_seq_stats* out, size_t count);

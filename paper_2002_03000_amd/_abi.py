@@ -14,6 +14,7 @@ PPERM_ROSENBLUTH = 2
 MODES = {"shared": PPERM_SHARED, "independent": PPERM_INDEPENDENT, "rosenbluth": PPERM_ROSENBLUTH}
 
 FLAG_GROUP_STATS = 1
+FLAG_OBSERVABLES = 2
 GROUPS = 16
 JOB_QUEUED, JOB_ACTIVE, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
 
@@ -41,7 +42,8 @@ class SeqStats(ctypes.Structure):
 class Layout(ctypes.Structure):
     _fields_ = [(f, ctypes.c_uint64) for f in ("G", "HG", "MG", "L", "m", "t", "stats",
                                                 "stack", "scratch", "ctrl", "total")] + \
-               [("row", ctypes.c_uint32), ("stack_slots", ctypes.c_uint32), ("groups", ctypes.c_uint64)]
+               [("row", ctypes.c_uint32), ("stack_slots", ctypes.c_uint32), ("groups", ctypes.c_uint64),
+                ("obs_L", ctypes.c_uint64), ("obs_G", ctypes.c_uint64)]
 
 
 class Job(ctypes.Structure):
@@ -84,6 +86,7 @@ SIGNATURES = {
                                     _c.POINTER(_c.c_double)]),
     "pperm_estimates": (_int, [_vp, _c.POINTER(_c.c_double), _c.POINTER(_u64), _c.POINTER(_u64), _sz]),
     "pperm_error_estimate": (_int, [_vp, _c.POINTER(_c.c_double), _c.POINTER(_c.c_double)]),
+    "pperm_observable_r2": (_int, [_vp, _c.POINTER(_c.c_double), _sz]),
     "pperm_sequence_stats": (_int, [_vp, _c.POINTER(SeqStats), _sz]),
     "pperm_stats": (_int, [_vp, _c.POINTER(SeqStats)]),
     "pperm_sync": (_int, [_vp]),

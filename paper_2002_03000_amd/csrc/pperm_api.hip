@@ -101,6 +101,11 @@ int resolve_shape(const pperm_config* c, Shape* sh) {
     sh->lds_wg_bytes = (wpw == 1) ? sh->lds_team_bytes + (uint32_t)align_up(c->n_max + 1u, 16) * 16u +
                                         LDS_STACK * (uint32_t)sizeof(StackEntry)
                                   : sh->lds_team_bytes * wpw;
+    // (observables) the sums of W * R^2 follow the copy stack
+    if (c->flags & PPERM_FLAG_OBSERVABLES) {
+        if (wpw != 1) return PPERM_EINVAL;
+        sh->lds_wg_bytes += (uint32_t)align_up(c->n_max + 1u, 16) * 16u;
+    }
     if (sh->lds_wg_bytes > (wpw == 1 ? kLdsLimit : kTeamLdsLimit)) return PPERM_EINVAL;
     return PPERM_OK;
 }
@@ -112,7 +117,8 @@ int validate(const pperm_config* c) {
     if (c->n_max < 1 || c->n_max > kMaxNmax) return PPERM_EINVAL;
     if (c->n_sequences < 1) return PPERM_EINVAL;
     if (c->mode > PPERM_ROSENBLUTH) return PPERM_EINVAL;
-    if ((c->flags & ~PPERM_FLAG_GROUP_STATS) != 0) return PPERM_EINVAL;
+    if ((c->flags & ~(PPERM_FLAG_GROUP_STATS | PPERM_FLAG_OBSERVABLES)) != 0) return PPERM_EINVAL;
+    if ((c->flags & PPERM_FLAG_OBSERVABLES) && c->mode == PPERM_INDEPENDENT) return PPERM_EINVAL;
     Shape sh;
     return resolve_shape(c, &sh);
 }
@@ -145,6 +151,10 @@ void compute_layout(const pperm_config* c, pperm_layout* L) {
     L->t = take(N * 8);
     L->stats = take(N * STATS_WORDS * 8);
     L->groups = take(GROUPS * (sizeof(SumRec) + 8));
+    if (c->flags & PPERM_FLAG_OBSERVABLES) {
+        L->obs_L = take(N * row * sizeof(SumRec));
+        L->obs_G = take(row * sizeof(SumRec));
+    }
     L->ctrl = take(CTRL_WORDS * 4 + sizeof(ProblemDesc));
     // private scratch, not zeroed: copy stacks, merge partials (records + counts, x2)
     L->stack = take(stack_slots * c->n_max * sizeof(StackEntry));
@@ -281,6 +291,7 @@ int pperm_create(const pperm_config* cfg, void* d_workspace, size_t bytes, void*
     d.lds_team_bytes = sh.lds_team_bytes;
     d.key0 = (uint32_t)cfg->seed;
     d.key1 = (uint32_t)(cfg->seed >> 32) ^ cfg->stream_id;
+    d.LR = (cfg->flags & PPERM_FLAG_OBSERVABLES) ? at<SumRec>(x, L.obs_L) : nullptr;
     x->desc_dev = reinterpret_cast<ProblemDesc*>(at<uint32_t>(x, L.ctrl) + CTRL_WORDS);
 
     // zero the state (G .. ctrl are contiguous) and seed the digests
@@ -344,7 +355,8 @@ int pperm_run_tours(pperm_ctx* x, uint32_t tours) {
         b.count = 1;
         b.total_items = N;
         b.queue = a.ctrl + CTRL_QUEUE;
-        HIP_TRY(launch_batch(b, x->workgroups, x->lds_wg_bytes, x->stream));
+        HIP_TRY(launch_batch(b, x->workgroups, x->lds_wg_bytes, x->stream,
+                             (x->cfg.flags & PPERM_FLAG_OBSERVABLES) != 0));
     } else {
         HIP_TRY(launch_run(a, x->cfg.dim, x->team_lanes, x->workgroups, x->lds_wg_bytes, x->stream));
     }
@@ -398,6 +410,26 @@ int pperm_merge_epoch(pperm_ctx* x) {
         a.zero = nullptr;
         a.rows = (uint32_t)((a.rows + 63) / 64);
         cur ^= 1;
+    }
+    if (x->cfg.flags & PPERM_FLAG_OBSERVABLES) {
+        // the sums of W * R^2 through the same tree (no counts)
+        SumRec* LR = at<SumRec>(x, x->lay.obs_L);
+        a.in = LR;
+        a.hin = nullptr;
+        a.zero = LR;
+        a.rows = N;
+        for (;;) {
+            const bool final_pass = (a.rows <= 64);
+            a.out = final_pass ? at<SumRec>(x, x->lay.obs_G) : bufd[cur];
+            a.hout = nullptr;
+            a.accumulate = final_pass ? 1u : 0u;
+            HIP_TRY(launch_merge_pass(a, x->stream));
+            if (final_pass) break;
+            a.in = bufd[cur];
+            a.zero = nullptr;
+            a.rows = (uint32_t)((a.rows + 63) / 64);
+            cur ^= 1;
+        }
     }
     x->merged_tours += (uint64_t)N * x->open_tours;
     x->open_tours = 0;
@@ -465,6 +497,7 @@ int pperm_run_batch(pperm_ctx* const* ctxs, size_t count, const uint32_t* tours_
     for (size_t i = 0; i < count; ++i) {
         pperm_ctx* x = ctxs[i];
         if (!x || x->device != device) return PPERM_EINVAL;
+        if (x->cfg.flags & PPERM_FLAG_OBSERVABLES) return PPERM_EINVAL;
         for (size_t j = 0; j < i; ++j)
             if (ctxs[j] == x) return PPERM_EINVAL;          // a problem at most once per batch
         if (tours_each[i] == 0) continue;
@@ -697,6 +730,7 @@ int job_validate(pperm_ctx* const* ctxs, const uint32_t* const* schedules, const
         pperm_ctx* x = ctxs[i];
         if (!x || x->device != device || x->team_lanes != 64) return PPERM_EINVAL;
         if (x->cfg.mode == PPERM_INDEPENDENT) return PPERM_EINVAL;
+        if (x->cfg.flags & PPERM_FLAG_OBSERVABLES) return PPERM_EINVAL;
         for (size_t j = 0; j < i; ++j)
             if (ctxs[j] == x) return PPERM_EINVAL;
         if (x->open_tours != 0) return PPERM_ESTATE;
@@ -1012,6 +1046,25 @@ int pperm_error_estimate(pperm_ctx* x, double* rel_err, double* log_groups) {
                                 : log(g.sum[k].m) + g.sum[k].e * ln2 - log((double)g.tours[k]);
     }
     *rel_err = defined ? group_rel_err(g.sum, g.tours, e_top) : INFINITY;
+    return PPERM_OK;
+}
+
+int pperm_observable_r2(pperm_ctx* x, double* out, size_t len) {
+    if (!x || !out) return PPERM_EINVAL;
+    if (!(x->cfg.flags & PPERM_FLAG_OBSERVABLES)) return PPERM_EINVAL;
+    const uint32_t n1 = x->cfg.n_max + 1;
+    if (len < n1) return PPERM_EINVAL;
+    int rc = check_device_errors(x);
+    if (rc) return rc;
+    if (x->merged_tours == 0) return PPERM_ESTATE;
+    std::vector<SumRec> G(n1), GR(n1);
+    HIP_TRY(hipMemcpy(G.data(), at<SumRec>(x, x->lay.G), n1 * sizeof(SumRec), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(GR.data(), at<SumRec>(x, x->lay.obs_G), n1 * sizeof(SumRec),
+                      hipMemcpyDeviceToHost));
+    // eqn (42MC): the pooled sum of W * R^2 over the pooled sum of W (the
+    // tour counts of numerator and denominator cancel)
+    for (uint32_t n = 0; n < n1; ++n)
+        out[n] = (G[n].m == 0.0) ? NAN : ldexp(GR[n].m / G[n].m, GR[n].e - G[n].e);
     return PPERM_OK;
 }
 

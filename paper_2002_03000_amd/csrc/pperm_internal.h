@@ -85,7 +85,8 @@ struct ProblemDesc {
     uint32_t slots_log2;
     uint32_t lds_team_bytes;   // occupancy table + slot ids; the sums row follows
     uint32_t key0, key1;
-    uint32_t pad[3];
+    uint32_t pad;
+    SumRec* LR;           // [N][row] per-sequence sums of W * R^2, or nullptr
 };
 
 // One problem's share of a launch: its tours, its step cap, and the index of
@@ -109,7 +110,7 @@ struct BatchArgs {
 struct MergeArgs {
     const SumRec* in;      // [rows][row]
     SumRec* out;           // [ceil(rows/64)][row], or G when final
-    uint64_t* hout;        // [ceil(rows/64)][row], or HG when final
+    uint64_t* hout;        // [ceil(rows/64)][row], or HG when final; nullptr: no counts
     const uint64_t* hin;   // later passes: [rows][row]; first pass: nullptr (counts in `in`)
     SumRec* zero;          // input to clear after reading (first pass) or nullptr
     uint32_t rows;
@@ -178,7 +179,8 @@ hipError_t launch_job(const JobArgs& a, uint32_t workgroups, uint32_t lds_bytes,
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t job_occupancy(uint32_t lds_bytes, int* blocks_per_cu);
 
-hipError_t launch_batch(const BatchArgs& b, uint32_t workgroups, uint32_t lds_bytes, hipStream_t s);
+hipError_t launch_batch(const BatchArgs& b, uint32_t workgroups, uint32_t lds_bytes, hipStream_t s,
+                        bool observables = false);
 hipError_t batch_occupancy(uint32_t lds_bytes, int* blocks_per_cu);
 hipError_t launch_merge_counts(const uint32_t* m, uint32_t N, uint64_t* MG, uint32_t* zero_m,
                                hipStream_t s);

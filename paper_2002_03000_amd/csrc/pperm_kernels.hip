@@ -629,7 +629,9 @@ __device__ __forceinline__ uint64_t fields_lanes(uint64_t hb) {
 // except where a lane index enters (scan windows, Philox counters, deletions).
 // A step issues its occupancy reads first, evaluates the prune/enrich
 // arithmetic while they are in flight, and only then resolves the scan.
-template <int D>
+// OBS: also record W * R^2 (squared end-to-end distance) at every arrival
+// beside the weight, the numerator of the ratio estimator of eqn (42MC).
+template <int D, bool OBS = false>
 __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t tours, uint32_t cap,
                                                   uint32_t s, unsigned char* lds, const SumRec* Gsrc,
                                                   bool fresh) {
@@ -646,6 +648,9 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
     uint16_t* sid = reinterpret_cast<uint16_t*>(lds + (sizeof(Key) << P.slots_log2));
     SumRec* Ls = reinterpret_cast<SumRec*>(lds + P.lds_team_bytes);
     StackEntry* lstk = reinterpret_cast<StackEntry*>(lds + P.lds_team_bytes + P.row * sizeof(SumRec));
+    // (observables) the sequence's per-length sums of W * R^2, after the stack
+    SumRec* LRs = reinterpret_cast<SumRec*>(lds + P.lds_team_bytes + P.row * sizeof(SumRec) +
+                                            LDS_STACK * sizeof(StackEntry));
     const int lane = (int)threadIdx.x;
     const uint32_t S = 1u << P.slots_log2;
     const uint32_t smask = S - 1u;
@@ -703,6 +708,9 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
         for (uint32_t i = (uint32_t)lane; i <= n_max; i += 64u) Ls[i] = z;
     } else {
         for (uint32_t i = (uint32_t)lane; i <= n_max; i += 64u) Ls[i] = load_global(Lrow + i);
+    }
+    if constexpr (OBS) {
+        for (uint32_t i = (uint32_t)lane; i <= n_max; i += 64u) LRs[i] = load_global(P.LR + rb0 + i);
     }
     wave_fence();
     SumRec rec0 = Ls[0];
@@ -773,6 +781,8 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
             uint32_t slot = (home + (uint32_t)poff) & smask;
             Key v = table[slot];
             const SumRec nxt = Ls[n + 1 + vz];
+            SumRec nxr = {0.0, 0, 0u};
+            if constexpr (OBS) nxr = LRs[n + 1 + vz];
             __builtin_amdgcn_sched_barrier(0);
 
             // ---- decision arithmetic while the reads are in flight ----
@@ -895,6 +905,19 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
                     nr.h = nxt.h + 1u;
                     if (lane == 0) Ls[n] = nr;
                     Lc = Lnew;
+                    if constexpr (OBS) {
+                        // R^2 of the new end, exact in FP64 (|coordinates| < 2^15)
+                        int x, y, z;
+                        L_::unpack(ekey, x, y, z);
+                        const double r2 = (double)x * (double)x + (double)y * (double)y +
+                                          (double)z * (double)z;
+                        const XF R = xf_add(xf_of(nxr), xf_mul(w, r2));
+                        SumRec rr;
+                        rr.m = R.m;
+                        rr.e = R.e;
+                        rr.h = 0u;
+                        if (lane == 0) LRs[n] = rr;
+                    }
                     if (cap != 0u && c_steps >= cap) {
                         abort = true;
                         break;
@@ -937,6 +960,9 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
     if (lane == 0) Ls[0] = rec0;
     wave_fence();
     for (uint32_t i = (uint32_t)lane; i <= n_max; i += 64u) store_global(Lrow + i, Ls[i]);
+    if constexpr (OBS) {
+        for (uint32_t i = (uint32_t)lane; i <= n_max; i += 64u) store_global(P.LR + rb0 + i, LRs[i]);
+    }
     if (lane == 0) {
         if (abort) atomicOr(&P.ctrl[CTRL_ERR], ERR_CAP);
         uint64_t* sr = P.stats + (size_t)s * STATS_WORDS;
@@ -958,7 +984,8 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
 // each wavefront takes the next item from a device queue until none is left.
 // A problem alone is a batch of one, so a problem's bits do not depend on what
 // else shares the launch.
-__global__ void __launch_bounds__(64) batch_kernel(BatchArgs B) {
+template <bool OBS>
+__device__ __forceinline__ void batch_body(const BatchArgs& B) {
     extern __shared__ __align__(16) unsigned char lds[];
     const int lane = (int)threadIdx.x;
     for (;;) {
@@ -981,10 +1008,15 @@ __global__ void __launch_bounds__(64) batch_kernel(BatchArgs B) {
         // make every field (and so the whole walk's control flow) non-uniform
         const ProblemDesc P = load_const(E.desc);
         const uint32_t s = item - E.first_item;
-        if (P.dim == 2) walk_sequence<2>(P, E.tours, E.step_cap, s, lds, P.G, false);
-        else walk_sequence<3>(P, E.tours, E.step_cap, s, lds, P.G, false);
+        if (P.dim == 2) walk_sequence<2, OBS>(P, E.tours, E.step_cap, s, lds, P.G, false);
+        else walk_sequence<3, OBS>(P, E.tours, E.step_cap, s, lds, P.G, false);
     }
 }
+
+__global__ void __launch_bounds__(64) batch_kernel(BatchArgs B) { batch_body<false>(B); }
+
+// The same over problems that also record W * R^2 (one problem per launch).
+__global__ void __launch_bounds__(64) batch_obs_kernel(BatchArgs B) { batch_body<true>(B); }
 
 // ---------------------------------------------------------------------------
 // Device-side epoch chaining.  Every problem runs its whole epoch schedule in
@@ -1331,14 +1363,14 @@ __global__ void __launch_bounds__(64) merge_pass_kernel(MergeArgs A) {
             const size_t o = (size_t)blockIdx.y * A.row + c;
             if (A.accumulate) {
                 vv = xf_add(xf_of(A.out[o]), vv);
-                hh += A.hout[o];
+                if (A.hout) hh += A.hout[o];
             }
             SumRec rec;
             rec.m = vv.m;
             rec.e = vv.e;
             rec.h = 0u;
             A.out[o] = rec;
-            A.hout[o] = hh;
+            if (A.hout) A.hout[o] = hh;
         }
     }
 }
@@ -1464,8 +1496,10 @@ hipError_t launch_init_state(uint64_t* stats, uint32_t N, void* zero_base, size_
         default: break;                                                 \
     }
 
-hipError_t launch_batch(const BatchArgs& b, uint32_t workgroups, uint32_t lds_bytes, hipStream_t s) {
-    hipLaunchKernelGGL(batch_kernel, dim3(workgroups), dim3(64), lds_bytes, s, b);
+hipError_t launch_batch(const BatchArgs& b, uint32_t workgroups, uint32_t lds_bytes, hipStream_t s,
+                        bool observables) {
+    if (observables) hipLaunchKernelGGL(batch_obs_kernel, dim3(workgroups), dim3(64), lds_bytes, s, b);
+    else hipLaunchKernelGGL(batch_kernel, dim3(workgroups), dim3(64), lds_bytes, s, b);
     return hipGetLastError();
 }
 

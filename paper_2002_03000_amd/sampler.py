@@ -20,12 +20,13 @@ class ParallelFlatPERM:
 
     def __init__(self, dim, n_max, n_sequences, seed, mode="shared", stream_id=0,
                  hash_slots=0, walks_per_wave=0, step_cap=0, group_stats=False, device=None,
-                 stream=None):
+                 stream=None, observables=False):
         lib = _abi.load()
         self.cfg = _abi.Config(ctypes.sizeof(_abi.Config), dim, n_max, n_sequences,
                                seed & 0xFFFFFFFFFFFFFFFF, _abi.MODES[mode], stream_id,
                                hash_slots, walks_per_wave, step_cap,
-                               _abi.FLAG_GROUP_STATS if group_stats else 0)
+                               (_abi.FLAG_GROUP_STATS if group_stats else 0) |
+                               (_abi.FLAG_OBSERVABLES if observables else 0))
         self.dim, self.n_max, self.N, self.mode = dim, n_max, n_sequences, mode
         self.device = torch.device(device if device is not None else "cuda")
         nbytes = ctypes.c_size_t()
@@ -88,6 +89,14 @@ class ParallelFlatPERM:
                    "pperm_error_estimate")
         return rel.value, lg
 
+    def observable_r2(self):
+        """<R^2_n>, the ratio estimator of eqn (42MC) for the squared end-to-end
+        distance, from the merged epochs (NaN where no sample reached n)."""
+        out = np.zeros(self.n_max + 1, dtype=np.float64)
+        _abi.check(self._lib.pperm_observable_r2(self._ctx, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                                 self.n_max + 1), "pperm_observable_r2")
+        return out
+
     def sync(self):
         _abi.check(self._lib.pperm_sync(self._ctx), "pperm_sync")
 
@@ -129,6 +138,8 @@ class ParallelFlatPERM:
             "stats": (torch.int64, (N, len(_abi.STATS_FIELDS))),
             "gsum": (torch.uint8, (_abi.GROUPS, 16)),
             "gtours": (torch.int64, (_abi.GROUPS,)),
+            "obs_L": (torch.uint8, (N, row, 16)),
+            "obs_G": (torch.uint8, (row, 16)),
         }
         dt, shape = shapes[name]
         off = {"gsum": lay.groups, "gtours": lay.groups + 16 * _abi.GROUPS}.get(name)
@@ -138,7 +149,8 @@ class ParallelFlatPERM:
         return self.workspace[off:off + nbytes].view(dt).view(shape)
 
     def records(self, name):
-        """Host copy of the G, L or gsum records as a structured numpy array (m, e, h)."""
+        """Host copy of the G, L, gsum, obs_L or obs_G records as a structured numpy
+        array (m, e, h)."""
         raw = self.view(name).cpu().numpy()
         return raw.reshape(raw.shape[:-1] + (16,)).view(self.RECORD_DTYPE)[..., 0]
 

@@ -17,7 +17,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared():
     src = open(os.path.join(ROOT, "include", "pperm.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(pperm_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(pperm_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_header_declares_the_method_calls():
@@ -49,7 +49,8 @@ def _ws(cfg):
 
 
 @pytest.mark.parametrize("bad", [dict(dim=1), dict(dim=4), dict(n_max=0), dict(n_max=32767),
-                                 dict(n_sequences=0), dict(mode=3), dict(flags=2),
+                                 dict(n_sequences=0), dict(mode=3), dict(flags=4),
+                                 dict(flags=2, mode=1), dict(flags=2, walks_per_wave=2),
                                  dict(hash_slots=100), dict(hash_slots=128, n_max=100),
                                  dict(walks_per_wave=3), dict(walks_per_wave=32),
                                  dict(dim=3, walks_per_wave=16)])
