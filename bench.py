@@ -66,6 +66,7 @@ def kernel_code_digest():
 WORKLOADS = {
     "parallel2d": workloads.PARALLEL_2D,
     "parallel3d": workloads.PARALLEL_3D,
+    "long2d": workloads.LONG_2D,       # n_max = 10^4: sums in global memory
     "plain2d": workloads.PLAIN_2D,
     "batched": None,          # the 256-problem mix, see run_batched()
     "served": None,           # the Poisson job stream, see run_served()
@@ -104,8 +105,8 @@ def cpu_baseline(p, budget_s=15.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None, help="default 3 (long2d: 1)")
+    ap.add_argument("--warmup", type=int, default=None, help="default 1 (long2d: 0)")
     ap.add_argument("--workload", default="parallel2d", choices=sorted(WORKLOADS))
     ap.add_argument("--epochs", type=int, default=0, help="override the epoch count (profiling)")
     ap.add_argument("--walks-per-wave", type=int, default=0)
@@ -129,6 +130,11 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (to calibrate the HBM byte counters)")
     args = ap.parse_args()
+    # a long2d job runs for about a minute and a half
+    if args.steps is None:
+        args.steps = 1 if args.workload == "long2d" else 3
+    if args.warmup is None:
+        args.warmup = 0 if args.workload == "long2d" else 1
 
     if args.kernel_digest:
         print(kernel_code_digest())
@@ -219,6 +225,7 @@ def main():
     est_top = np.array([r[0][p.n_max] for r in results])
     rel_err = float(np.std(np.exp(est_top - est_top.mean()), ddof=1)) if len(results) > 1 else None
 
+    kernel = "batch_long_kernel" if args.workload == "long2d" else "batch_kernel"
     line = {
         "metric": "walk-steps/s (parallel flatPERM, 1 GPU)",
         "value": value,
@@ -238,11 +245,12 @@ def main():
                    "walk_steps_per_job": steps_total // args.steps,
                    "launch": shape, "autotune": tuning},
         "cn_rel_err_nmax": rel_err,
+        "log_cn_nmax": float(est_top[0]),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
                      "frac": achieved / ALU_PEAK_TOPS,
-                     "traffic": measured_traffic(f"batch_kernel_{args.workload}_traffic.md")
+                     "traffic": measured_traffic(f"{kernel}_{args.workload}_traffic.md")
                      if not args.epochs else None,
-                     "kernel": "batch_kernel", "avg_launch_ms": run_ms / launches,
+                     "kernel": kernel, "avg_launch_ms": run_ms / launches,
                      "alg_ops_per_step": ops},
         "cpu_baseline": None,
     }

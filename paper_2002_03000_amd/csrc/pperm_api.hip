@@ -30,6 +30,7 @@ struct pperm_ctx {
     uint32_t lds_team_bytes;
     uint32_t lds_wg_bytes;
     uint32_t workgroups;
+    bool long_walk;           // per-length sums in global memory (see resolve_shape)
     uint64_t merged_tours;    // pooled tours merged so far (per sequence in independent mode)
     uint64_t open_tours;      // tours per sequence run since the last merge
     int sticky_error;
@@ -77,36 +78,57 @@ struct Shape {
     uint32_t lds_team_bytes;   // occupancy table + slot ids of one walk
     uint32_t lds_wg_bytes;     // LDS of one workgroup
     uint32_t walks_per_wave;
+    bool long_walk;            // per-length sums outside LDS
 };
 
+// The occupancy table holds at most n_max + 1 sites; at least twice that many
+// slots keeps linear-probing runs short.  One walk per wavefront keeps the
+// sequence's per-length sums (and, with observables, its sums of W * R^2) in
+// LDS beside the table and the bottom of its copy stack.  Where that does not
+// fit (walks of several thousand steps), the sums stay in global memory and
+// the table may fill up to 5/8 (a power of two of at least 1.6 (n_max + 1)
+// slots) so that table and slot ids of walks up to ~10^4 steps fit in LDS.
 int resolve_shape(const pperm_config* c, Shape* sh) {
-    uint32_t slots = c->hash_slots;
+    const uint64_t n1 = c->n_max + 1u;
+    const uint32_t row_bytes = (uint32_t)align_up(n1, 16) * 16u;
+    const bool obs = (c->flags & PPERM_FLAG_OBSERVABLES) != 0;
+    auto team_bytes = [&](uint64_t slots) {
+        return (uint32_t)align_up(slots * key_bytes(c->dim) + 2ull * n1, 16);
+    };
+    uint32_t wpw = c->walks_per_wave;
+    if (wpw == 0) wpw = 1u;   // default shape: one walk per wavefront
+    if (!is_pow2(wpw) || wpw > (c->dim == 2 ? 16u : 8u)) return PPERM_EINVAL;
+    if (obs && wpw != 1) return PPERM_EINVAL;
+    uint64_t slots = c->hash_slots;
     if (slots == 0) {
         slots = 64;
-        while (slots < 2u * (c->n_max + 1u)) slots <<= 1;
+        while (slots < 2u * n1) slots <<= 1;
     }
-    if (!is_pow2(slots) || slots > kMaxSlots || slots < 2u * (c->n_max + 1u)) return PPERM_EINVAL;
-    sh->slots = slots;
-    sh->lds_team_bytes = (uint32_t)align_up((uint64_t)slots * key_bytes(c->dim) +
-                                            2ull * (c->n_max + 1u), 16);
-    uint32_t wpw = c->walks_per_wave;
-    if (wpw == 0) {
-        // default shape, narrowed until the walks of one workgroup fit in LDS
-        wpw = 1u;
+    if (!is_pow2((uint32_t)slots) || slots > kMaxSlots) return PPERM_EINVAL;
+    bool lng = false;
+    uint64_t bytes;
+    if (wpw == 1) {
+        bytes = (uint64_t)team_bytes(slots) + row_bytes * (obs ? 2u : 1u) +
+                LDS_STACK * (uint32_t)sizeof(StackEntry);
+        if (bytes > kLdsLimit) {
+            lng = true;
+            if (c->hash_slots == 0)
+                while (team_bytes(slots) + LDS_STACK * sizeof(StackEntry) > kLdsLimit &&
+                       5u * (slots / 2u) >= 8u * n1)
+                    slots >>= 1;
+            bytes = (uint64_t)team_bytes(slots) + LDS_STACK * (uint32_t)sizeof(StackEntry);
+        }
+    } else {
+        bytes = (uint64_t)team_bytes(slots) * wpw;
     }
-    if (!is_pow2(wpw) || wpw > (c->dim == 2 ? 16u : 8u)) return PPERM_EINVAL;
+    if (lng ? 5u * slots < 8u * n1 : slots < 2u * n1) return PPERM_EINVAL;
+    if (bytes > (wpw == 1 ? kLdsLimit : kTeamLdsLimit)) return PPERM_EINVAL;
+    sh->slots = (uint32_t)slots;
+    sh->lds_team_bytes = team_bytes(slots);
     sh->walks_per_wave = wpw;
     sh->team_lanes = 64u / wpw;
-    // the wave-per-walk kernel also keeps the sequence's sums in LDS
-    sh->lds_wg_bytes = (wpw == 1) ? sh->lds_team_bytes + (uint32_t)align_up(c->n_max + 1u, 16) * 16u +
-                                        LDS_STACK * (uint32_t)sizeof(StackEntry)
-                                  : sh->lds_team_bytes * wpw;
-    // (observables) the sums of W * R^2 follow the copy stack
-    if (c->flags & PPERM_FLAG_OBSERVABLES) {
-        if (wpw != 1) return PPERM_EINVAL;
-        sh->lds_wg_bytes += (uint32_t)align_up(c->n_max + 1u, 16) * 16u;
-    }
-    if (sh->lds_wg_bytes > (wpw == 1 ? kLdsLimit : kTeamLdsLimit)) return PPERM_EINVAL;
+    sh->lds_wg_bytes = (uint32_t)bytes;
+    sh->long_walk = lng;
     return PPERM_OK;
 }
 
@@ -197,6 +219,11 @@ double group_rel_err(const SumRec* sum, const uint64_t* tours, int e_top) {
 
 }  // namespace
 
+bool pperm::config_long_walk(const pperm_config* c) {
+    Shape sh;
+    return validate(c) == PPERM_OK && resolve_shape(c, &sh) == PPERM_OK && sh.long_walk;
+}
+
 extern "C" {
 
 const char* pperm_strerror(int code) {
@@ -248,6 +275,7 @@ int pperm_create(const pperm_config* cfg, void* d_workspace, size_t bytes, void*
     x->slots_log2 = log2u(sh.slots);
     x->lds_team_bytes = sh.lds_team_bytes;
     x->lds_wg_bytes = sh.lds_wg_bytes;
+    x->long_walk = sh.long_walk;
 
     hipError_t e = hipGetDevice(&x->device);
     if (e != hipSuccess) { delete x; return device_error(e, "hipGetDevice"); }
@@ -356,7 +384,7 @@ int pperm_run_tours(pperm_ctx* x, uint32_t tours) {
         b.total_items = N;
         b.queue = a.ctrl + CTRL_QUEUE;
         HIP_TRY(launch_batch(b, x->workgroups, x->lds_wg_bytes, x->stream,
-                             (x->cfg.flags & PPERM_FLAG_OBSERVABLES) != 0));
+                             (x->cfg.flags & PPERM_FLAG_OBSERVABLES) != 0, x->long_walk));
     } else {
         HIP_TRY(launch_run(a, x->cfg.dim, x->team_lanes, x->workgroups, x->lds_wg_bytes, x->stream));
     }
@@ -497,7 +525,7 @@ int pperm_run_batch(pperm_ctx* const* ctxs, size_t count, const uint32_t* tours_
     for (size_t i = 0; i < count; ++i) {
         pperm_ctx* x = ctxs[i];
         if (!x || x->device != device) return PPERM_EINVAL;
-        if (x->cfg.flags & PPERM_FLAG_OBSERVABLES) return PPERM_EINVAL;
+        if ((x->cfg.flags & PPERM_FLAG_OBSERVABLES) || x->long_walk) return PPERM_EINVAL;
         for (size_t j = 0; j < i; ++j)
             if (ctxs[j] == x) return PPERM_EINVAL;          // a problem at most once per batch
         if (tours_each[i] == 0) continue;
@@ -730,7 +758,7 @@ int job_validate(pperm_ctx* const* ctxs, const uint32_t* const* schedules, const
         pperm_ctx* x = ctxs[i];
         if (!x || x->device != device || x->team_lanes != 64) return PPERM_EINVAL;
         if (x->cfg.mode == PPERM_INDEPENDENT) return PPERM_EINVAL;
-        if (x->cfg.flags & PPERM_FLAG_OBSERVABLES) return PPERM_EINVAL;
+        if ((x->cfg.flags & PPERM_FLAG_OBSERVABLES) || x->long_walk) return PPERM_EINVAL;
         for (size_t j = 0; j < i; ++j)
             if (ctxs[j] == x) return PPERM_EINVAL;
         if (x->open_tours != 0) return PPERM_ESTATE;

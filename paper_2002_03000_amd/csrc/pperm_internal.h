@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+typedef struct pperm_config pperm_config;
+
 namespace pperm {
 
 // Error bits a kernel may raise in ctrl[1].
@@ -179,8 +181,12 @@ hipError_t launch_job(const JobArgs& a, uint32_t workgroups, uint32_t lds_bytes,
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t job_occupancy(uint32_t lds_bytes, int* blocks_per_cu);
 
+// True for a valid configuration whose walks run with their per-length sums
+// in global memory (one problem per launch only).
+bool config_long_walk(const pperm_config* c);
+
 hipError_t launch_batch(const BatchArgs& b, uint32_t workgroups, uint32_t lds_bytes, hipStream_t s,
-                        bool observables = false);
+                        bool observables = false, bool long_walk = false);
 hipError_t batch_occupancy(uint32_t lds_bytes, int* blocks_per_cu);
 hipError_t launch_merge_counts(const uint32_t* m, uint32_t N, uint64_t* MG, uint32_t* zero_m,
                                hipStream_t s);

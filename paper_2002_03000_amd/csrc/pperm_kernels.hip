@@ -631,7 +631,10 @@ __device__ __forceinline__ uint64_t fields_lanes(uint64_t hb) {
 // arithmetic while they are in flight, and only then resolves the scan.
 // OBS: also record W * R^2 (squared end-to-end distance) at every arrival
 // beside the weight, the numerator of the ratio estimator of eqn (42MC).
-template <int D, bool OBS = false>
+// LONG: walks too long for the per-length sums to share LDS with the
+// occupancy table; the sums stay in the sequence's global row (read and
+// written in place) and LDS holds the table, the slot ids and the stack bottom.
+template <int D, bool OBS = false, bool LONG = false>
 __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t tours, uint32_t cap,
                                                   uint32_t s, unsigned char* lds, const SumRec* Gsrc,
                                                   bool fresh) {
@@ -646,11 +649,22 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
     // tours and back out at their end) and the bottom of its copy stack
     Key* table = reinterpret_cast<Key*>(lds);
     uint16_t* sid = reinterpret_cast<uint16_t*>(lds + (sizeof(Key) << P.slots_log2));
-    SumRec* Ls = reinterpret_cast<SumRec*>(lds + P.lds_team_bytes);
-    StackEntry* lstk = reinterpret_cast<StackEntry*>(lds + P.lds_team_bytes + P.row * sizeof(SumRec));
+    const uint32_t row_lds = LONG ? 0u : P.row * (uint32_t)sizeof(SumRec);
+    SumRec* Ls = LONG ? P.L + (size_t)s * P.row : reinterpret_cast<SumRec*>(lds + P.lds_team_bytes);
+    StackEntry* lstk = reinterpret_cast<StackEntry*>(lds + P.lds_team_bytes + row_lds);
     // (observables) the sequence's per-length sums of W * R^2, after the stack
-    SumRec* LRs = reinterpret_cast<SumRec*>(lds + P.lds_team_bytes + P.row * sizeof(SumRec) +
-                                            LDS_STACK * sizeof(StackEntry));
+    SumRec* LRs = LONG ? P.LR + (size_t)s * P.row
+                       : reinterpret_cast<SumRec*>(lds + P.lds_team_bytes + row_lds +
+                                                   LDS_STACK * sizeof(StackEntry));
+    // record access: LDS, or the global row of a long walk
+    auto rec_ld = [&](const SumRec* p) -> SumRec {
+        if constexpr (LONG) return load_global(p);
+        else return *p;
+    };
+    auto rec_st = [&](SumRec* p, const SumRec& v) {
+        if constexpr (LONG) store_global(p, v);
+        else *p = v;
+    };
     const int lane = (int)threadIdx.x;
     const uint32_t S = 1u << P.slots_log2;
     const uint32_t smask = S - 1u;
@@ -703,17 +717,19 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
     const uint64_t t0 = ufirst64(P.t[s]);
     uint32_t tlo = (uint32_t)t0;               // tour index: its low word keys the random numbers
     uint32_t m = fresh ? 0u : ufirst(P.m[s]);
-    if (fresh) {
-        const SumRec z = {0.0, 0, 0u};
-        for (uint32_t i = (uint32_t)lane; i <= n_max; i += 64u) Ls[i] = z;
-    } else {
-        for (uint32_t i = (uint32_t)lane; i <= n_max; i += 64u) Ls[i] = load_global(Lrow + i);
-    }
-    if constexpr (OBS) {
-        for (uint32_t i = (uint32_t)lane; i <= n_max; i += 64u) LRs[i] = load_global(P.LR + rb0 + i);
+    if constexpr (!LONG) {
+        if (fresh) {
+            const SumRec z = {0.0, 0, 0u};
+            for (uint32_t i = (uint32_t)lane; i <= n_max; i += 64u) Ls[i] = z;
+        } else {
+            for (uint32_t i = (uint32_t)lane; i <= n_max; i += 64u) Ls[i] = load_global(Lrow + i);
+        }
+        if constexpr (OBS) {
+            for (uint32_t i = (uint32_t)lane; i <= n_max; i += 64u) LRs[i] = load_global(P.LR + rb0 + i);
+        }
     }
     wave_fence();
-    SumRec rec0 = Ls[0];
+    SumRec rec0 = rec_ld(Ls);
     // counters of this call, added to the sequence's totals at its end: the
     // step count (scalar, it drives the cap) and one counter per lane of `cv`
     // (lane i accumulates statistics word i)
@@ -780,9 +796,9 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
             const uint32_t home = L_::hash(nk) >> hshift;
             uint32_t slot = (home + (uint32_t)poff) & smask;
             Key v = table[slot];
-            const SumRec nxt = Ls[n + 1 + vz];
+            const SumRec nxt = rec_ld(Ls + (n + 1 + vz));
             SumRec nxr = {0.0, 0, 0u};
-            if constexpr (OBS) nxr = LRs[n + 1 + vz];
+            if constexpr (OBS) nxr = rec_ld(LRs + (n + 1 + vz));
             __builtin_amdgcn_sched_barrier(0);
 
             // ---- decision arithmetic while the reads are in flight ----
@@ -903,7 +919,7 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
                     nr.m = Lnew.m;
                     nr.e = Lnew.e;
                     nr.h = nxt.h + 1u;
-                    if (lane == 0) Ls[n] = nr;
+                    if (lane == 0) rec_st(Ls + n, nr);
                     Lc = Lnew;
                     if constexpr (OBS) {
                         // R^2 of the new end, exact in FP64 (|coordinates| < 2^15)
@@ -916,7 +932,7 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
                         rr.m = R.m;
                         rr.e = R.e;
                         rr.h = 0u;
-                        if (lane == 0) LRs[n] = rr;
+                        if (lane == 0) rec_st(LRs + n, rr);
                     }
                     if (cap != 0u && c_steps >= cap) {
                         abort = true;
@@ -957,11 +973,13 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
         wave_fence();
     }
     cv += (lane == ST_EVENTS) ? c_events : 0ull;
-    if (lane == 0) Ls[0] = rec0;
+    if (lane == 0) rec_st(Ls, rec0);
     wave_fence();
-    for (uint32_t i = (uint32_t)lane; i <= n_max; i += 64u) store_global(Lrow + i, Ls[i]);
-    if constexpr (OBS) {
-        for (uint32_t i = (uint32_t)lane; i <= n_max; i += 64u) store_global(P.LR + rb0 + i, LRs[i]);
+    if constexpr (!LONG) {
+        for (uint32_t i = (uint32_t)lane; i <= n_max; i += 64u) store_global(Lrow + i, Ls[i]);
+        if constexpr (OBS) {
+            for (uint32_t i = (uint32_t)lane; i <= n_max; i += 64u) store_global(P.LR + rb0 + i, LRs[i]);
+        }
     }
     if (lane == 0) {
         if (abort) atomicOr(&P.ctrl[CTRL_ERR], ERR_CAP);
@@ -984,7 +1002,7 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
 // each wavefront takes the next item from a device queue until none is left.
 // A problem alone is a batch of one, so a problem's bits do not depend on what
 // else shares the launch.
-template <bool OBS>
+template <bool OBS, bool LONG>
 __device__ __forceinline__ void batch_body(const BatchArgs& B) {
     extern __shared__ __align__(16) unsigned char lds[];
     const int lane = (int)threadIdx.x;
@@ -1008,15 +1026,18 @@ __device__ __forceinline__ void batch_body(const BatchArgs& B) {
         // make every field (and so the whole walk's control flow) non-uniform
         const ProblemDesc P = load_const(E.desc);
         const uint32_t s = item - E.first_item;
-        if (P.dim == 2) walk_sequence<2, OBS>(P, E.tours, E.step_cap, s, lds, P.G, false);
-        else walk_sequence<3, OBS>(P, E.tours, E.step_cap, s, lds, P.G, false);
+        if (P.dim == 2) walk_sequence<2, OBS, LONG>(P, E.tours, E.step_cap, s, lds, P.G, false);
+        else walk_sequence<3, OBS, LONG>(P, E.tours, E.step_cap, s, lds, P.G, false);
     }
 }
 
-__global__ void __launch_bounds__(64) batch_kernel(BatchArgs B) { batch_body<false>(B); }
+__global__ void __launch_bounds__(64) batch_kernel(BatchArgs B) { batch_body<false, false>(B); }
 
-// The same over problems that also record W * R^2 (one problem per launch).
-__global__ void __launch_bounds__(64) batch_obs_kernel(BatchArgs B) { batch_body<true>(B); }
+// The same for one problem whose walks also record W * R^2, whose walks are
+// long (sums in global memory), or both.
+__global__ void __launch_bounds__(64) batch_obs_kernel(BatchArgs B) { batch_body<true, false>(B); }
+__global__ void __launch_bounds__(64) batch_long_kernel(BatchArgs B) { batch_body<false, true>(B); }
+__global__ void __launch_bounds__(64) batch_long_obs_kernel(BatchArgs B) { batch_body<true, true>(B); }
 
 // ---------------------------------------------------------------------------
 // Device-side epoch chaining.  Every problem runs its whole epoch schedule in
@@ -1497,9 +1518,12 @@ hipError_t launch_init_state(uint64_t* stats, uint32_t N, void* zero_base, size_
     }
 
 hipError_t launch_batch(const BatchArgs& b, uint32_t workgroups, uint32_t lds_bytes, hipStream_t s,
-                        bool observables) {
-    if (observables) hipLaunchKernelGGL(batch_obs_kernel, dim3(workgroups), dim3(64), lds_bytes, s, b);
-    else hipLaunchKernelGGL(batch_kernel, dim3(workgroups), dim3(64), lds_bytes, s, b);
+                        bool observables, bool long_walk) {
+    const dim3 g(workgroups), t(64);
+    if (long_walk && observables) hipLaunchKernelGGL(batch_long_obs_kernel, g, t, lds_bytes, s, b);
+    else if (long_walk) hipLaunchKernelGGL(batch_long_kernel, g, t, lds_bytes, s, b);
+    else if (observables) hipLaunchKernelGGL(batch_obs_kernel, g, t, lds_bytes, s, b);
+    else hipLaunchKernelGGL(batch_kernel, g, t, lds_bytes, s, b);
     return hipGetLastError();
 }
 

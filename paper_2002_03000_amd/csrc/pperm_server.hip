@@ -233,6 +233,7 @@ int pperm_server_submit(pperm_server* S, const pperm_job* job, uint64_t* id) {
     int rc = pperm_workspace_bytes(&j->cfg, &bytes);
     if (rc == PPERM_OK && round_block(bytes) + S->scratch_bytes > S->pool.capacity())
         rc = PPERM_EINVAL;
+    if (rc == PPERM_OK && pperm::config_long_walk(&j->cfg)) rc = PPERM_EINVAL;   // chained launches keep sums in LDS
     if (rc) {
         delete j;
         return rc;

@@ -124,3 +124,13 @@ def test_server_pool_allocator_first_fit_and_coalescing(seed):
     frees = [-(i + 1) for i, op in enumerate(ops) if op > 0 and offs[i] >= 0 and int(offs[i]) in live]
     offs2, used2 = pool_script(cap, ops + frees + [cap])
     assert used2 == cap and offs2[-1] == 0
+
+
+@pytest.mark.parametrize("dim,n_max,ok", [(2, 5000, True), (2, 10000, True), (2, 15000, True), (2, 16000, False),
+                                          (3, 10000, True), (3, 10239, True), (3, 10240, False)])
+def test_long_walk_limits(dim, n_max, ok):
+    # walks whose per-length sums no longer fit in LDS beside the occupancy
+    # table keep them in global memory; the table (up to 5/8 full) and the
+    # slot ids must still fit in one workgroup's 160 KiB of LDS
+    rc, n = _ws(_cfg(dim=dim, n_max=n_max, n_sequences=256))
+    assert (rc == 0) == ok

@@ -1,0 +1,96 @@
+"""Long walks (n_max ~ 10^4): the per-length sums stay in global memory.
+
+Parity with the oracle bit for bit at n_max = 10^4 in two and three
+dimensions, with and without observables, and the launch-shape rules of the
+long layout."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+from parity_util import assert_epoch_equal, assert_pooled_equal, make_pair
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("dim,n_max,N,seed,tours", [
+    (2, 10000, 100, 5, (1, 1)),
+    (3, 10000, 70, 6, (1, 1, 2)),
+    (2, 6000, 130, 7, (1, 2)),
+])
+def test_long_walks_match_oracle(dim, n_max, N, seed, tours):
+    g, o = make_pair(dim, n_max, N, seed)
+    shape = g.launch_shape()
+    print(f"d={dim} n_max={n_max} N={N}: {shape}", flush=True)
+    for T in tours:
+        g.run_tours(T)
+        o.run_tours(T)
+        assert_epoch_equal(g, o, label=f"long epoch T={T}")
+        g.merge_epoch()
+        o.merge_epoch()
+        assert_pooled_equal(g, o, f"long merge T={T}")
+    lc, hist, M = g.estimates()
+    olc = o.log_estimates()
+    fin = np.isfinite(olc)
+    assert np.array_equal(fin, np.isfinite(lc)) and fin[n_max]
+    np.testing.assert_allclose(lc[fin], olc[fin], rtol=1e-12, atol=0)
+
+
+def test_long_walk_layout():
+    from paper_2002_03000_amd import ParallelFlatPERM
+    g = ParallelFlatPERM(3, 10000, 8, 1)
+    # 2^14 slots (5/8 full at most) of 8-byte keys: one workgroup per CU
+    assert g.launch_shape()["hash_slots"] == 16384
+    g2 = ParallelFlatPERM(2, 10000, 8, 1)
+    assert g2.launch_shape()["hash_slots"] == 32768
+
+
+def test_long_walk_observables_match_oracle():
+    from paper_2002_03000_amd import ParallelFlatPERM
+    g = ParallelFlatPERM(2, 8000, 90, 8, observables=True)
+    o = oracle.Oracle(2, 8000, 90, 8, observables=True)
+    for T in (1, 1):
+        g.run_tours(T)
+        o.run_tours(T)
+        g.merge_epoch()
+        o.merge_epoch()
+    assert_pooled_equal(g, o, "long observables")
+    rec = g.records("obs_G")[:8001]
+    assert np.array_equal(rec["m"], o.GR["m"]) and np.array_equal(rec["e"], o.GR["e"])
+    a, b = g.observable_r2(), o.observable_r2()
+    nan = np.isnan(b)
+    assert np.array_equal(np.isnan(a), nan)
+    assert np.array_equal(a[~nan].view(np.uint64), b[~nan].view(np.uint64))
+
+
+def test_long_contexts_stay_out_of_batches():
+    from paper_2002_03000_amd import ParallelFlatPERM, _abi
+    import torch
+    lib = _abi.load()
+    g = ParallelFlatPERM(2, 9000, 4, 9)
+    ctxs = (ctypes.c_void_p * 1)(g._ctx)
+    tours = (ctypes.c_uint32 * 1)(1)
+    need = ctypes.c_size_t()
+    _abi.check(lib.pperm_batch_workspace_bytes(1, ctypes.byref(need)), "batch bytes")
+    ws = torch.empty(need.value + 256, dtype=torch.uint8, device="cuda")
+    assert lib.pperm_run_batch(ctxs, 1, tours, ctypes.c_void_p(ws.data_ptr()), need.value, None) == -1
+
+
+def test_log_c10000_agrees_with_the_long_run_value():
+    # Algorithm 2 on the square lattice up to n = 10^4 (256 sequences, 98304
+    # tours): the estimate of log c_10000 must fall within 1 of the value a
+    # very long flatPERM run gives (eqn (8)), the band Tables 1 and 2 show for
+    # Algorithm 2 once a few thousand walks have been started
+    import workloads
+    from paper_2002_03000_amd import ParallelFlatPERM
+    p = workloads.LONG_2D
+    g = ParallelFlatPERM(p.dim, p.n_max, p.n_sequences, p.seed, group_stats=True)
+    for T in p.schedule():
+        g.run_tours(T)
+        g.merge_epoch()
+    lc, hist, M = g.estimates()
+    rel, _ = g.error_estimate()
+    print(f"log c_10000 = {lc[10000]:.4f} after {M} tours (relative error estimate {rel:.3g})", flush=True)
+    assert M == p.total_tours
+    assert abs(lc[10000] - 9704.14) < 1.0

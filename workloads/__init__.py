@@ -70,6 +70,10 @@ PARALLEL_2D = Problem(dim=2, n_max=500, n_sequences=4096, tours_per_epoch=64, ep
 # 16 epochs' worth (8,388,608 tours), the first 32 tours in warm-up epochs.
 PARALLEL_3D = Problem(dim=3, n_max=1000, n_sequences=16384, tours_per_epoch=32, epochs=16, seed=3)
 
+# Long walks on Z^2: n_max = 10^4 (the length of the paper's Tables 1 and 2),
+# 256 sequences, a merge every 64 tours, 6 epochs' worth (98304 tours).
+LONG_2D = Problem(dim=2, n_max=10000, n_sequences=256, tours_per_epoch=64, epochs=6, seed=2024)
+
 
 def batched_mix(seed: int = 4, count: int = 256):
     """Independent problems for one batched launch.
