@@ -125,6 +125,8 @@ def main():
     ap.add_argument("--serve-pool-gib", type=float, default=64.0)
     ap.add_argument("--serve-max-sequences", type=int, default=262144)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-latency-bound", action="store_true",
+                    help="skip the critical-path replay that follows the timed region")
     ap.add_argument("--kernel-digest", action="store_true",
                     help="print the digest that keys the committed counter summaries")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -254,9 +256,55 @@ def main():
                      "alg_ops_per_step": ops},
         "cpu_baseline": None,
     }
+    if not args.no_latency_bound:
+        line["latency_bound"] = latency_bound(p, make, sched, elapsed / args.steps)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(p)
     print(json.dumps(line), flush=True)
+
+
+def latency_bound(p, make, sched, seconds_per_job):
+    """The floor an epoch-synchronous job cannot go below on any number of
+    waves: each epoch lasts at least as long as its heaviest sequence takes,
+    one step after another on one wave.  Measured outside the timed region:
+    the first timed job is replayed (same seed, same bits) with every
+    sequence's step count read after each epoch, and the latency of one step
+    of a wave running alone comes from a one-sequence problem of the same
+    dimension and length."""
+    import numpy as np
+    import torch
+    from paper_2002_03000_amd import ParallelFlatPERM
+    g = make(p.seed)
+    prev = np.zeros(p.n_sequences, dtype=np.uint64)
+    crit = 0
+    for T in sched:
+        g.run_tours(T)
+        g.merge_epoch()
+        st = g.sequence_stats()["steps"]
+        crit += int((st - prev).max())
+        prev = st
+    g.close()
+    # one wave alone: a single sequence through the same schedule (the first
+    # epochs warm its own estimates), timed over the full-length epochs
+    lone = ParallelFlatPERM(p.dim, p.n_max, 1, p.seed + 77)
+    head = len(sched) - p.epochs + 1
+    for T in sched[:head]:
+        lone.run_tours(T)
+        lone.merge_epoch()
+    torch.cuda.synchronize()
+    s0 = lone.stats()["steps"]
+    t0 = time.perf_counter()
+    for T in sched[head:head + 8]:
+        lone.run_tours(T)
+        lone.merge_epoch()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    lone_steps = lone.stats()["steps"] - s0
+    lone.close()
+    t_step = dt / max(lone_steps, 1)
+    bound = crit * t_step
+    return {"critical_path_steps": crit, "lone_step_us": t_step * 1e6, "lone_sample_steps": int(lone_steps),
+            "bound_ms_per_step": bound * 1e3, "frac": bound / seconds_per_job}
 
 
 def copy_calibration(nbytes=1 << 30):
