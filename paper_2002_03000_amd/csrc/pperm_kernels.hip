@@ -103,6 +103,42 @@ __device__ __forceinline__ double xf_ratio(XF a, XF b) {
     return r;
 }
 
+// The same operations where an operand is known to be nonzero (every walk
+// weight and every sum that includes one): they give the same result as the
+// general ones on such operands, with the zero cases left out.
+__device__ __forceinline__ XF xf_norm_nz(double x, int e) {
+    XF r;
+    r.m = __builtin_amdgcn_frexp_mant(x);
+    r.e = e + __builtin_amdgcn_frexp_exp(x);
+    return r;
+}
+
+// a + b for b != 0: a zero a is shifted away like a negligible one (its
+// mantissa is 0, so the sum is exactly b).
+__device__ __forceinline__ XF xf_add_nz(XF a, XF b) {
+    const bool sw = (a.m == 0.0) || (a.e < b.e);
+    const double hm = sw ? b.m : a.m;
+    const int he = sw ? b.e : a.e;
+    const double lm = sw ? a.m : b.m;
+    const int le = sw ? a.e : b.e;
+    const int d = he - le;
+    const double ls = (d > 63) ? 0.0 : ldexp(lm, -d);
+    return xf_norm_nz(hm + ls, he);
+}
+
+__device__ __forceinline__ XF xf_mul_nz(XF a, double k) { return xf_norm_nz(a.m * k, a.e); }
+__device__ __forceinline__ XF xf_div_nz(XF a, double k) { return xf_norm_nz(a.m / k, a.e); }
+
+// a / b for a, b != 0.
+__device__ __forceinline__ double xf_ratio_nz(XF a, XF b) {
+    const int d = a.e - b.e;
+    const int dc = d < -1000 ? -1000 : (d > 1000 ? 1000 : d);
+    double r = ldexp(a.m / b.m, dc);
+    r = (d > 1000) ? 0x1p1000 : r;
+    r = (d < -1000) ? 0.0 : r;
+    return r;
+}
+
 __device__ __forceinline__ XF xf_of(const SumRec& r) { return XF{r.m, r.e}; }
 
 // ---------------------------------------------------------------------------
@@ -547,6 +583,9 @@ __device__ __forceinline__ uint32_t lane_value(uint32_t v, uint32_t l) {
 __device__ __forceinline__ uint64_t lane_value(uint64_t v, uint32_t l) {
     return ((uint64_t)lane_value((uint32_t)(v >> 32), l) << 32) | (uint64_t)lane_value((uint32_t)v, l);
 }
+__device__ __forceinline__ double lane_value(double v, uint32_t l) {
+    return __builtin_bit_cast(double, lane_value(__builtin_bit_cast(uint64_t, v), l));
+}
 
 // Address-space views.  The pooled sums are never written while a growth
 // launch runs, so uniform reads of them may go through the constant space
@@ -757,6 +796,7 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
         uint32_t k = 0, kb = 0;
         bool stale = true;
         uint4 rb = make_uint4(0, 0, 0, 0);
+        double ul = 0.0;                       // this lane's block as a 53-bit uniform
         uint32_t n = 0;
         Key ekey = origin_key;                 // the walk's end
         bool control = false;
@@ -777,11 +817,12 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
                 kb = k;
                 stale = false;
                 rb = philox10(make_uint4(kb + (uint32_t)lane, 0u, tt, s), P.key0, P.key1);
+                // u of each lane's block, formed once per 64 events (exact:
+                // integers below 2^53 and power-of-two scalings)
+                ul = ((double)(rb.y >> 5) * 67108864.0 + (double)(rb.z >> 6)) * (1.0 / 9007199254740992.0);
             }
             const uint32_t li = k - kb;
             const uint32_t B0 = __builtin_amdgcn_readlane(rb.x, li);
-            const uint32_t B1 = __builtin_amdgcn_readlane(rb.y, li);
-            const uint32_t B2 = __builtin_amdgcn_readlane(rb.z, li);
             // pooled sums: this length's (loaded a step ago) and the next one's,
             // which the following step uses if this one grows the walk (a step
             // never starts at n_max, so n + 1 is inside the row)
@@ -803,18 +844,20 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
 
             // ---- decision arithmetic while the reads are in flight ----
             // eqn (6): r = W / [W_n], [W_n] = sum / seen (own epoch data weighted
-            // N in Algorithm 2), evaluated as (W * seen) / sum; only used when a
-            // decision is due at this length
-            const XF sum = xf_add(Gc, xf_mul(Lc, pool));
-            const double r = xf_ratio(xf_mul(w, seen), sum);
-            const double u = ((double)(B1 >> 5) * 67108864.0 + (double)(B2 >> 6)) *
-                             (1.0 / 9007199254740992.0);
-            const double f = floor(r);
-            const uint32_t ub = ufirst((r >= 1.0 ? 1u : 0u) |
-                                       ((r != f && u < (f + 1.0) - r) ? 2u : 0u) |
-                                       (r == f ? 4u : 0u) | (u < r ? 8u : 0u));
-            // (r is only meaningful when a decision is due; keep the conversion defined)
-            const uint32_t fi = ufirst((uint32_t)((f >= 0.0 && f < 4294967295.0) ? f : 0.0));
+            // N in Algorithm 2), evaluated as (W * seen) / sum; only when a
+            // decision is due at this length (not after a resume or at n = 0)
+            XF sum = {0.0, 0};
+            uint32_t ub = 0u, fi = 0u;
+            if (control) {
+                sum = xf_add_nz(Gc, xf_mul_nz(Lc, pool));
+                const double r = xf_ratio_nz(xf_mul_nz(w, seen), sum);
+                const double u = lane_value(ul, li);
+                const double f = floor(r);
+                ub = ufirst((r >= 1.0 ? 1u : 0u) | ((r != f && u < (f + 1.0) - r) ? 2u : 0u) |
+                            (r == f ? 4u : 0u) | (u < r ? 8u : 0u));
+                // (keep the conversion defined for every r)
+                fi = ufirst((uint32_t)((f >= 0.0 && f < 4294967295.0) ? f : 0.0));
+            }
             asm volatile("" ::"s"(ub), "s"(fi));
 
             // ---- resolve the scan: one window per pass, usually one pass ----
@@ -856,7 +899,7 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
                         // r >= 1: c = floor(r) with probability ceil(r) - r, else ceil(r)
                         const uint32_t ci = (ub & 6u) ? fi : fi + 1u;
                         if (ci > 1u) {
-                            w = xf_div(w, (double)ci);
+                            w = xf_div_nz(w, (double)ci);
                             if (sp > 0u) {
                                 // the old top goes to position sp - 1
                                 StackEntry e;
@@ -882,7 +925,7 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
                                   : ((lane == ST_COPIES) ? (uint64_t)(ci - 1u) : 0ull);
                         }
                     } else if (ub & 8u) {
-                        w = xf_div(sum, seen);     // r < 1, survives: W / r
+                        w = xf_div_nz(sum, seen);  // r < 1, survives: W / r
                     } else {
                         pruned = true;             // r < 1, pruned with probability 1 - r
                     }
@@ -909,12 +952,12 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
                     // W *= a_+, eqn (2).  No range check is needed here: |e|
                     // grows by at most 3 per step and falls by at most 33 per
                     // decision, so it stays below 2^21 for every n_max allowed.
-                    w = xf_mul(w, (double)a);
+                    w = xf_mul_nz(w, (double)a);
                     n += 1;
                     c_steps += 1;
                     Gpre = Gnx;
                     // ---- arrival: record into the running sums, eqn (4) ----
-                    const XF Lnew = xf_add(xf_of(nxt), w);
+                    const XF Lnew = xf_add_nz(xf_of(nxt), w);
                     SumRec nr;
                     nr.m = Lnew.m;
                     nr.e = Lnew.e;
@@ -927,7 +970,7 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
                         L_::unpack(ekey, x, y, z);
                         const double r2 = (double)x * (double)x + (double)y * (double)y +
                                           (double)z * (double)z;
-                        const XF R = xf_add(xf_of(nxr), xf_mul(w, r2));
+                        const XF R = xf_add_nz(xf_of(nxr), xf_mul_nz(w, r2));
                         SumRec rr;
                         rr.m = R.m;
                         rr.e = R.e;
