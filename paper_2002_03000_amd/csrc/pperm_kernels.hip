@@ -860,32 +860,34 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
             }
             asm volatile("" ::"s"(ub), "s"(fi));
 
-            // ---- resolve the scan: one window per pass, usually one pass ----
-            uint64_t pending = F::HI;          // directions not yet resolved
-            uint64_t freem = 0;                // directions resolved free
-            uint64_t insm = 0;                 // empty lanes of the window that resolved them
+            // ---- resolve the scan: usually the first window settles every direction ----
+            uint64_t freem;                    // directions resolved free
+            uint64_t insm;                     // per direction: empty lanes of the window that resolved it
             uint32_t myslot = slot;            // this lane's slot in that window
-            uint32_t base = (uint32_t)poff;
-            bool first = true;
-            for (;;) {
-                const uint64_t act = fields_lanes<D>(pending);
-                const uint64_t hitm = __ballot(v == nk) & act;
-                const uint64_t empm = __ballot(v == (Key)0) & act;
-                const uint64_t hd = fields_any<D>(hitm);
+            {
+                const uint64_t hd = fields_any<D>(__ballot(v == nk));
+                const uint64_t empm = __ballot(v == (Key)0);
                 const uint64_t ed = fields_any<D>(empm);
-                const uint64_t fr = ed & ~hd;
-                freem |= fr;
-                pending &= ~(hd | ed);
-                const uint64_t frl = fields_lanes<D>(fr);
-                insm |= empm & frl;
-                if (pending == 0u && first) break;
-                if ((frl >> lane) & 1u) myslot = slot;
-                if (pending == 0u) break;
-                // a run longer than the window: read the next W positions
-                first = false;
-                base += W;
-                slot = (home + base) & smask;
-                v = table[slot];
+                freem = ed & ~hd;
+                insm = empm;                   // (only fields of free directions are read)
+                uint64_t pending = F::HI & ~(hd | ed);
+                uint32_t base = (uint32_t)poff;
+                while (pending != 0u) {
+                    // a run longer than the window: read the next W positions
+                    base += W;
+                    slot = (home + base) & smask;
+                    v = table[slot];
+                    const uint64_t act = fields_lanes<D>(pending);
+                    const uint64_t hd2 = fields_any<D>(__ballot(v == nk) & act);
+                    const uint64_t emp2 = __ballot(v == (Key)0) & act;
+                    const uint64_t ed2 = fields_any<D>(emp2);
+                    const uint64_t fr = ed2 & ~hd2;
+                    freem |= fr;
+                    pending &= ~(hd2 | ed2);
+                    const uint64_t frl = fields_lanes<D>(fr);
+                    insm = (insm & ~frl) | (emp2 & frl);
+                    if ((frl >> lane) & 1u) myslot = slot;
+                }
             }
             const uint32_t a = (uint32_t)__popcll(freem);
             if (a == 0u) {
