@@ -730,7 +730,7 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
     const uint32_t n_max = P.n_max;
     const uint32_t row = P.row;
     const bool shared_mode = (P.mode == MODE_SHARED);
-    const bool control_mode = (P.mode != MODE_ROSENBLUTH);
+    const uint32_t control_mode = (P.mode != MODE_ROSENBLUTH) ? 1u : 0u;
     const double pool = shared_mode ? (double)P.N : 1.0;
     const uint64_t pool_u = shared_mode ? (uint64_t)P.N : 1ull;
 
@@ -773,6 +773,7 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
     // step count (scalar, it drives the cap) and one counter per lane of `cv`
     // (lane i accumulates statistics word i)
     uint32_t c_steps = 0, c_tours = 0, c_maxd = 0;
+    const uint32_t capv = cap ? cap : 0xFFFFFFFFu;   // step cap of this call (0: none)
     uint64_t c_events = 0;                     // events: the sum over tours of k
     uint64_t cv = 0;
     uint64_t digest = ufirst64(P.stats[(size_t)s * STATS_WORDS + ST_DIGEST]);
@@ -799,7 +800,7 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
         double ul = 0.0;                       // this lane's block as a 53-bit uniform
         uint32_t n = 0;
         Key ekey = origin_key;                 // the walk's end
-        bool control = false;
+        uint32_t control = 0u;                 // a decision is due at this length
         // pending copies: the top entry in scalar registers, the others at
         // positions 0 .. sp-2 (LDS below LDS_STACK, global memory above)
         uint32_t sp = 0, top_n = 0, top_rem = 0;
@@ -979,7 +980,7 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
                         rr.h = 0u;
                         if (lane == 0) rec_st(LRs + n, rr);
                     }
-                    if (cap != 0u && c_steps >= cap) {
+                    if (c_steps >= capv) {
                         abort = true;
                         break;
                     }
@@ -1008,7 +1009,7 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
                 // LIFO deletion of sites rn+1..n restores the table exactly
                 for (uint32_t i = rn + 1u + (uint32_t)lane; i <= n; i += 64u) table[sid[i]] = (Key)0;
                 n = rn;
-                control = false;
+                control = 0u;
                 wave_fence();
             }
         }
