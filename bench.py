@@ -111,6 +111,9 @@ def main():
     ap.add_argument("--epochs", type=int, default=0, help="override the epoch count (profiling)")
     ap.add_argument("--walks-per-wave", type=int, default=0)
     ap.add_argument("--hash-slots", type=int, default=0)
+    ap.add_argument("--sums-global", choices=("auto", "on", "off"), default="auto",
+                    help="launch tuning: per-length sums in global memory, more walks per CU "
+                         "(auto: on for parallel3d, whose in-LDS sums allow only four walks per CU)")
     ap.add_argument("--autotune", action="store_true", help="pick the launch shape by short trial runs first")
     ap.add_argument("--problems", type=int, default=0, help="batched: use the first P problems of the mix")
     ap.add_argument("--lockstep", action="store_true",
@@ -132,6 +135,10 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (to calibrate the HBM byte counters)")
     args = ap.parse_args()
+    if args.sums_global == "auto":
+        args.sums_global = (args.workload == "parallel3d")
+    else:
+        args.sums_global = (args.sums_global == "on")
     # a long2d job runs for about a minute and a half
     if args.steps is None:
         args.steps = 1 if args.workload == "long2d" else 3
@@ -175,10 +182,12 @@ def main():
         from paper_2002_03000_amd import autotune
         best, tuning = autotune(p.dim, p.n_max, p.n_sequences, mode=p.mode, trial=tuple(p.schedule()[:5]))
         args.walks_per_wave, args.hash_slots = best["walks_per_wave"], best["hash_slots"]
+        args.sums_global = best["sums_global"]
 
     def make(seed):
         return ParallelFlatPERM(p.dim, p.n_max, p.n_sequences, seed, mode=p.mode,
-                                walks_per_wave=args.walks_per_wave, hash_slots=args.hash_slots)
+                                walks_per_wave=args.walks_per_wave, hash_slots=args.hash_slots,
+                                sums_global=args.sums_global)
 
     sched = p.schedule()
 
@@ -227,7 +236,7 @@ def main():
     est_top = np.array([r[0][p.n_max] for r in results])
     rel_err = float(np.std(np.exp(est_top - est_top.mean()), ddof=1)) if len(results) > 1 else None
 
-    kernel = "batch_long_kernel" if args.workload == "long2d" else "batch_kernel"
+    kernel = "batch_long_kernel" if (args.workload == "long2d" or args.sums_global) else "batch_kernel"
     line = {
         "metric": "walk-steps/s (parallel flatPERM, 1 GPU)",
         "value": value,
@@ -245,7 +254,7 @@ def main():
                    "n_sequences": p.n_sequences, "tours_per_epoch": p.tours_per_epoch,
                    "epochs": len(sched), "schedule": sched[:len(sched) - p.epochs + 2],
                    "walk_steps_per_job": steps_total // args.steps,
-                   "launch": shape, "autotune": tuning},
+                   "launch": dict(shape, sums_global=bool(args.sums_global)), "autotune": tuning},
         "cn_rel_err_nmax": rel_err,
         "log_cn_nmax": float(est_top[0]),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
@@ -257,13 +266,13 @@ def main():
         "cpu_baseline": None,
     }
     if not args.no_latency_bound:
-        line["latency_bound"] = latency_bound(p, make, sched, elapsed / args.steps)
+        line["latency_bound"] = latency_bound(p, make, sched, elapsed / args.steps, args.sums_global)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(p)
     print(json.dumps(line), flush=True)
 
 
-def latency_bound(p, make, sched, seconds_per_job):
+def latency_bound(p, make, sched, seconds_per_job, sums_global=False):
     """The floor an epoch-synchronous job cannot go below on any number of
     waves: each epoch lasts at least as long as its heaviest sequence takes,
     one step after another on one wave.  Measured outside the timed region:
@@ -286,7 +295,7 @@ def latency_bound(p, make, sched, seconds_per_job):
     g.close()
     # one wave alone: a single sequence through the same schedule (the first
     # epochs warm its own estimates), timed over the full-length epochs
-    lone = ParallelFlatPERM(p.dim, p.n_max, 1, p.seed + 77)
+    lone = ParallelFlatPERM(p.dim, p.n_max, 1, p.seed + 77, sums_global=sums_global)
     head = len(sched) - p.epochs + 1
     for T in sched[:head]:
         lone.run_tours(T)

@@ -66,7 +66,7 @@ typedef struct pperm_config {
     uint32_t step_cap;        /* growth steps per sequence per pperm_run_tours call after
                                  which the sequence stops with PPERM_EOVERFLOW; 0 = the
                                  watchdog default min(2^31, 4096 * tours * (n_max + 1))  */
-    uint32_t flags;           /* PPERM_FLAG_GROUP_STATS | PPERM_FLAG_OBSERVABLES, or 0     */
+    uint32_t flags;           /* PPERM_FLAG_GROUP_STATS | _OBSERVABLES | _SUMS_GLOBAL, or 0 */
 } pperm_config;
 
 /* Keep 16 group sums of the weights recorded at n_max (sequence s in group
@@ -82,6 +82,13 @@ typedef struct pperm_config {
  * through pperm_run_tours / pperm_merge_epoch (and their graphs) only.  The
  * walks themselves, and every other result, are unchanged. */
 #define PPERM_FLAG_OBSERVABLES  2u
+
+/* Launch tuning: keep each sequence's per-length sums in its global row even
+ * where they would fit in LDS beside the occupancy table.  Less LDS per walk
+ * lets more walks share a compute unit, at the cost of a global read per
+ * step; results never change.  Needs one walk per wavefront; such contexts
+ * run through pperm_run_tours / pperm_merge_epoch (and their graphs) only. */
+#define PPERM_FLAG_SUMS_GLOBAL  4u
 
 /* Per-sequence counters, cumulative over the context's life (10 x uint64 each). */
 typedef struct pperm_seq_stats {

@@ -15,6 +15,7 @@ MODES = {"shared": PPERM_SHARED, "independent": PPERM_INDEPENDENT, "rosenbluth":
 
 FLAG_GROUP_STATS = 1
 FLAG_OBSERVABLES = 2
+FLAG_SUMS_GLOBAL = 4
 GROUPS = 16
 JOB_QUEUED, JOB_ACTIVE, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
 

@@ -85,7 +85,8 @@ struct Shape {
 // slots keeps linear-probing runs short.  One walk per wavefront keeps the
 // sequence's per-length sums (and, with observables, its sums of W * R^2) in
 // LDS beside the table and the bottom of its copy stack.  Where that does not
-// fit (walks of several thousand steps), the sums stay in global memory and
+// fit (walks of several thousand steps), or where PPERM_FLAG_SUMS_GLOBAL asks
+// for more walks per compute unit, the sums stay in global memory and
 // the table may fill up to 5/8 (a power of two of at least 1.6 (n_max + 1)
 // slots) so that table and slot ids of walks up to ~10^4 steps fit in LDS.
 int resolve_shape(const pperm_config* c, Shape* sh) {
@@ -98,7 +99,8 @@ int resolve_shape(const pperm_config* c, Shape* sh) {
     uint32_t wpw = c->walks_per_wave;
     if (wpw == 0) wpw = 1u;   // default shape: one walk per wavefront
     if (!is_pow2(wpw) || wpw > (c->dim == 2 ? 16u : 8u)) return PPERM_EINVAL;
-    if (obs && wpw != 1) return PPERM_EINVAL;
+    const bool force_global = (c->flags & PPERM_FLAG_SUMS_GLOBAL) != 0;
+    if ((obs || force_global) && wpw != 1) return PPERM_EINVAL;
     uint64_t slots = c->hash_slots;
     if (slots == 0) {
         slots = 64;
@@ -110,7 +112,7 @@ int resolve_shape(const pperm_config* c, Shape* sh) {
     if (wpw == 1) {
         bytes = (uint64_t)team_bytes(slots) + row_bytes * (obs ? 2u : 1u) +
                 LDS_STACK * (uint32_t)sizeof(StackEntry);
-        if (bytes > kLdsLimit) {
+        if (bytes > kLdsLimit || force_global) {
             lng = true;
             if (c->hash_slots == 0)
                 while (team_bytes(slots) + LDS_STACK * sizeof(StackEntry) > kLdsLimit &&
@@ -139,7 +141,8 @@ int validate(const pperm_config* c) {
     if (c->n_max < 1 || c->n_max > kMaxNmax) return PPERM_EINVAL;
     if (c->n_sequences < 1) return PPERM_EINVAL;
     if (c->mode > PPERM_ROSENBLUTH) return PPERM_EINVAL;
-    if ((c->flags & ~(PPERM_FLAG_GROUP_STATS | PPERM_FLAG_OBSERVABLES)) != 0) return PPERM_EINVAL;
+    if ((c->flags & ~(PPERM_FLAG_GROUP_STATS | PPERM_FLAG_OBSERVABLES | PPERM_FLAG_SUMS_GLOBAL)) != 0)
+        return PPERM_EINVAL;
     if ((c->flags & PPERM_FLAG_OBSERVABLES) && c->mode == PPERM_INDEPENDENT) return PPERM_EINVAL;
     Shape sh;
     return resolve_shape(c, &sh);

@@ -20,13 +20,14 @@ class ParallelFlatPERM:
 
     def __init__(self, dim, n_max, n_sequences, seed, mode="shared", stream_id=0,
                  hash_slots=0, walks_per_wave=0, step_cap=0, group_stats=False, device=None,
-                 stream=None, observables=False):
+                 stream=None, observables=False, sums_global=False):
         lib = _abi.load()
         self.cfg = _abi.Config(ctypes.sizeof(_abi.Config), dim, n_max, n_sequences,
                                seed & 0xFFFFFFFFFFFFFFFF, _abi.MODES[mode], stream_id,
                                hash_slots, walks_per_wave, step_cap,
                                (_abi.FLAG_GROUP_STATS if group_stats else 0) |
-                               (_abi.FLAG_OBSERVABLES if observables else 0))
+                               (_abi.FLAG_OBSERVABLES if observables else 0) |
+                               (_abi.FLAG_SUMS_GLOBAL if sums_global else 0))
         self.dim, self.n_max, self.N, self.mode = dim, n_max, n_sequences, mode
         self.device = torch.device(device if device is not None else "cuda")
         nbytes = ctypes.c_size_t()
@@ -389,43 +390,47 @@ def pool_script(pool_bytes, ops):
 
 def autotune(dim, n_max, n_sequences, mode="shared", trial=(1, 1, 2, 4, 8), seed=0x5EED,
              walks_per_wave=(1, 2, 4, 8), slot_factors=(1, 2), device=None):
-    """Choose the launch shape (walks per wave, hash slots) for a configuration
-    by timing a short trial schedule of every candidate on a scratch problem
-    with its own seed.  Launch shapes never change a result, so the choice
-    is free.  Returns (best, table): best = {"walks_per_wave", "hash_slots",
-    "ms"}, table = one such dict per candidate that fits the device."""
+    """Choose the launch shape (walks per wave, hash slots, and for one walk
+    per wave whether the per-length sums stay in global memory) for a
+    configuration by timing a short trial schedule of every candidate on a
+    scratch problem with its own seed.  Launch shapes never change a result,
+    so the choice is free.  Returns (best, table): best = {"walks_per_wave",
+    "hash_slots", "sums_global", "ms"}, table = one such dict per candidate
+    that fits the device."""
     device = torch.device(device if device is not None else "cuda")
     s0 = 64
     while s0 < 2 * (n_max + 1):
         s0 *= 2
     table = []
     warmed = False
-    for wpw in walks_per_wave:
-        for f in slot_factors:
-            slots = s0 * f
-            try:
-                g = ParallelFlatPERM(dim, n_max, n_sequences, seed, mode=mode, hash_slots=slots,
-                                     walks_per_wave=wpw, device=device)
-            except _abi.PPermError:
-                continue                      # does not fit (LDS or lane count)
-            if not warmed:
-                for T in trial[:2]:
-                    g.run_tours(T)
-                    g.merge_epoch()
-                g.sync()
-                g.close()
-                g = ParallelFlatPERM(dim, n_max, n_sequences, seed, mode=mode, hash_slots=slots,
-                                     walks_per_wave=wpw, device=device)
-                warmed = True
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record(g.stream)
-            for T in trial:
+    shapes = [(wpw, s0 * f, sg) for wpw in walks_per_wave for f in slot_factors
+              for sg in ((False, True) if wpw == 1 else (False,))]
+    for wpw, slots, sg in shapes:
+        def make():
+            return ParallelFlatPERM(dim, n_max, n_sequences, seed, mode=mode, hash_slots=slots,
+                                    walks_per_wave=wpw, device=device, sums_global=sg)
+        try:
+            g = make()
+        except _abi.PPermError:
+            continue                      # does not fit (LDS or lane count)
+        if not warmed:
+            for T in trial[:2]:
                 g.run_tours(T)
                 g.merge_epoch()
-            b.record(g.stream)
             g.sync()
-            table.append({"walks_per_wave": wpw, "hash_slots": slots, "ms": a.elapsed_time(b)})
             g.close()
+            g = make()
+            warmed = True
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(g.stream)
+        for T in trial:
+            g.run_tours(T)
+            g.merge_epoch()
+        b.record(g.stream)
+        g.sync()
+        table.append({"walks_per_wave": wpw, "hash_slots": slots, "sums_global": sg,
+                      "ms": a.elapsed_time(b)})
+        g.close()
     if not table:
         raise RuntimeError("no launch shape fits this configuration")
     best = min(table, key=lambda r: r["ms"])

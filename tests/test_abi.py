@@ -49,7 +49,7 @@ def _ws(cfg):
 
 
 @pytest.mark.parametrize("bad", [dict(dim=1), dict(dim=4), dict(n_max=0), dict(n_max=32767),
-                                 dict(n_sequences=0), dict(mode=3), dict(flags=4),
+                                 dict(n_sequences=0), dict(mode=3), dict(flags=8), dict(flags=4, walks_per_wave=4),
                                  dict(flags=2, mode=1), dict(flags=2, walks_per_wave=2),
                                  dict(hash_slots=100), dict(hash_slots=128, n_max=100),
                                  dict(walks_per_wave=3), dict(walks_per_wave=32),

@@ -60,7 +60,9 @@ def test_autotune_picks_a_fitting_shape_with_identical_results():
     best, table = autotune(2, 120, 256, trial=(1, 1, 2))
     print(table, flush=True)
     assert best in table and len(table) >= 2
-    tuned = ParallelFlatPERM(2, 120, 256, 64, hash_slots=best["hash_slots"], walks_per_wave=best["walks_per_wave"])
+    assert any(r["sums_global"] for r in table)
+    tuned = ParallelFlatPERM(2, 120, 256, 64, hash_slots=best["hash_slots"], walks_per_wave=best["walks_per_wave"],
+                             sums_global=best["sums_global"])
     plain = ParallelFlatPERM(2, 120, 256, 64)
     for g in (tuned, plain):
         for T in (1, 1, 2, 4):

@@ -94,3 +94,23 @@ def test_log_c10000_agrees_with_the_long_run_value():
     print(f"log c_10000 = {lc[10000]:.4f} after {M} tours (relative error estimate {rel:.3g})", flush=True)
     assert M == p.total_tours
     assert abs(lc[10000] - 9704.14) < 1.0
+
+
+@pytest.mark.parametrize("dim,n_max,N,seed", [(3, 1000, 200, 21), (2, 500, 130, 22)])
+def test_sums_in_global_memory_change_no_bit(dim, n_max, N, seed):
+    # the tuning flag that keeps the per-length sums out of LDS (more walks per
+    # compute unit) runs the long-walk walker at ordinary lengths: same bits as
+    # the oracle and as the default layout
+    from paper_2002_03000_amd import ParallelFlatPERM
+    g = ParallelFlatPERM(dim, n_max, N, seed, sums_global=True)
+    h = ParallelFlatPERM(dim, n_max, N, seed)
+    o = oracle.Oracle(dim, n_max, N, seed)
+    for T in (1, 1, 2):
+        for x in (g, h, o):
+            x.run_tours(T)
+        assert_epoch_equal(g, o, label=f"sums in global memory T={T}")
+        for x in (g, h, o):
+            x.merge_epoch()
+        assert_pooled_equal(g, o, "sums in global memory")
+    a, b = g.sequence_stats(), h.sequence_stats()
+    assert all(np.array_equal(a[f], b[f]) for f in a.dtype.names)
