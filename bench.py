@@ -484,8 +484,9 @@ def run_batched(args, plain_budget_s=40.0):
 def run_served(args, plain_budget_s=30.0):
     """A Poisson stream of sampling jobs served with continuous batching: jobs
     arrive in real time, are admitted by workspace footprint and active
-    sequences, advance one epoch per server step together with every other
-    active job, and retire at the first merge that meets their stop rule."""
+    sequences, advance their epochs at their own pace in each server step (one
+    time-sliced chained launch over every active job), and retire at the first
+    merge that meets their stop rule."""
     import numpy as np
     import torch
     from paper_2002_03000_amd import Server
@@ -597,7 +598,7 @@ def run_served(args, plain_budget_s=30.0):
                                  f"in {plain_dt:.2f} s"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
                      "frac": achieved / ALU_PEAK_TOPS, "traffic": None,
-                     "kernel": "server step (batch_kernel + merges)", "avg_launch_ms": gpu_ms / max(1, n_steps),
+                     "kernel": "server step (job_kernel, time-sliced)", "avg_launch_ms": gpu_ms / max(1, n_steps),
                      "alg_ops_per_step": ops},
         "cpu_baseline": None,
     }
