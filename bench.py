@@ -223,8 +223,11 @@ def main():
     elapsed = time.perf_counter() - t0
 
     steps_total = 0
+    scans_total = 0                    # a_+ evaluations: one per growth event or trapped walk
     for g in ctxs:
-        steps_total += g.stats()["steps"]
+        st = g.stats()
+        steps_total += st["steps"]
+        scans_total += st["events"] + st["traps"]
     run_ms = sum(a.elapsed_time(b) for a, b in events)
     launches = len(events)
     shape = ctxs[0].launch_shape()
@@ -257,6 +260,7 @@ def main():
                    "launch": dict(shape, sums_global=bool(args.sums_global)), "autotune": tuning},
         "cn_rel_err_nmax": rel_err,
         "log_cn_nmax": float(est_top[0]),
+        "a_plus_evaluations_per_step": scans_total / steps_total,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
                      "frac": achieved / ALU_PEAK_TOPS,
                      "traffic": measured_traffic(f"{kernel}_{args.workload}_traffic.md")
