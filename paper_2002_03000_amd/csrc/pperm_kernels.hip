@@ -948,10 +948,6 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
                         (uint32_t)__builtin_ctz((uint32_t)(insm >> (dir * W)) & FIELD) + (uint32_t)(dir * W);
                     const uint32_t ins_slot = __builtin_amdgcn_readlane(myslot, il);
                     ekey = lane_value(nk, il);
-                    if (lane == 0) {
-                        table[ins_slot] = ekey;
-                        sid[n + 1] = (uint16_t)ins_slot;
-                    }
                     // W *= a_+, eqn (2).  No range check is needed here: |e|
                     // grows by at most 3 per step and falls by at most 33 per
                     // decision, so it stays below 2^21 for every n_max allowed.
@@ -960,12 +956,18 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
                     c_steps += 1;
                     Gpre = Gnx;
                     // ---- arrival: record into the running sums, eqn (4) ----
+                    // (formed before the table insert, so that waiting for the
+                    // record read never waits for the insert's LDS writes too)
                     const XF Lnew = xf_add_nz(xf_of(nxt), w);
                     SumRec nr;
                     nr.m = Lnew.m;
                     nr.e = Lnew.e;
                     nr.h = nxt.h + 1u;
-                    if (lane == 0) rec_st(Ls + n, nr);
+                    if (lane == 0) {
+                        table[ins_slot] = ekey;
+                        sid[n] = (uint16_t)ins_slot;
+                        rec_st(Ls + n, nr);
+                    }
                     Lc = Lnew;
                     if constexpr (OBS) {
                         // R^2 of the new end, exact in FP64 (|coordinates| < 2^15)
