@@ -170,7 +170,8 @@ int pperm_batch_workspace_bytes(size_t count, size_t* bytes);
  * context on `hip_stream`).  d_workspace: caller-owned device memory of at least
  * pperm_batch_workspace_bytes(count), 256-byte aligned, not in use by another
  * batch in flight.  Not thread-safe per device.  Errors: EINVAL (bad arguments,
- * a context twice, contexts on another device), EOVERFLOW, EDEVICE. */
+ * a context twice, contexts on another device, a context with observables or
+ * with its per-length sums in global memory), EOVERFLOW, EDEVICE. */
 int pperm_run_batch(pperm_ctx* const* ctxs, size_t count, const uint32_t* tours_each,
                     void* d_workspace, size_t bytes, void* hip_stream);
 
@@ -201,8 +202,9 @@ int pperm_job_workspace_bytes(pperm_ctx* const* ctxs, const uint32_t* epochs, si
  * must be ordered after all earlier work of the contexts.  d_workspace:
  * caller-owned device memory of pperm_job_workspace_bytes, 256-byte aligned.
  * Errors: EINVAL (bad arguments, a zero entry in a schedule, a context twice,
- * another device, PPERM_INDEPENDENT mode, several walks per wave), ESTATE (a
- * context with unmerged tours), EOVERFLOW, EDEVICE. */
+ * another device, PPERM_INDEPENDENT mode, several walks per wave, observables,
+ * per-length sums in global memory), ESTATE (a context with unmerged tours),
+ * EOVERFLOW, EDEVICE. */
 int pperm_run_job(pperm_ctx* const* ctxs, const uint32_t* const* schedules, const uint32_t* epochs,
                   size_t count, void* d_workspace, size_t bytes, void* hip_stream);
 
@@ -300,7 +302,7 @@ typedef struct pperm_job {
     double target_rel_err;     /* stop at the first merge with pperm_error_estimate <= this
                                   (0: no such stop)                                       */
     uint64_t tour_cap;         /* stop at the first merge where the pooled tours M reach
-                                  this (M summed over sequences in PPERM_INDEPENDENT mode) */
+                                  this                                                    */
 } pperm_job;
 
 #define PPERM_JOB_QUEUED  0u
@@ -326,10 +328,13 @@ int pperm_server_create(void* d_pool, size_t pool_bytes, uint32_t max_active_seq
                         void* hip_stream, pperm_server** out);
 
 /* Queue a job; *id receives its id (1, 2, ...).  The job is validated here
- * (EINVAL for a bad description or one that can never fit the pool). */
+ * (EINVAL for a bad description, PPERM_INDEPENDENT mode, a length whose sums no
+ * longer fit in LDS beside the occupancy table, or a job that can never fit
+ * the pool; EOVERFLOW when tour_cap + N * T would pass 2^32 - 1). */
 int pperm_server_submit(pperm_server* srv, const pperm_job* job, uint64_t* id);
 
-/* One scheduling step (admit, one batched epoch, merges, stop rules); writes
+/* One scheduling step (admit, one time slice of chained epochs with the stop
+ * rules evaluated on the device, retire); writes
  * the ids of the jobs retired by this step into finished[0 .. cap) and their
  * number into *n_finished (may exceed cap; the rest are still retired).
  * Synchronises.  A job whose own calls fail is retired as PPERM_JOB_FAILED;
