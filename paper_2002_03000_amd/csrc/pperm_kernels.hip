@@ -854,8 +854,10 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
                 const double r = xf_ratio_nz(xf_mul_nz(w, seen), sum);
                 const double u = lane_value(ul, li);
                 const double f = floor(r);
-                ub = ufirst((r >= 1.0 ? 1u : 0u) | ((r != f && u < (f + 1.0) - r) ? 2u : 0u) |
-                            (r == f ? 4u : 0u) | (u < r ? 8u : 0u));
+                // bit 0: r >= 1; bit 1: keep floor(r) copies (r integral, or u
+                // below ceil(r) - r); bit 3: a walk with r < 1 survives
+                ub = ufirst((r >= 1.0 ? 1u : 0u) | ((r == f || u < (f + 1.0) - r) ? 2u : 0u) |
+                            (u < r ? 8u : 0u));
                 // (keep the conversion defined for every r)
                 fi = ufirst((uint32_t)((f >= 0.0 && f < 4294967295.0) ? f : 0.0));
             }
@@ -900,7 +902,7 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
                 if (control) {
                     if (ub & 1u) {
                         // r >= 1: c = floor(r) with probability ceil(r) - r, else ceil(r)
-                        const uint32_t ci = (ub & 6u) ? fi : fi + 1u;
+                        const uint32_t ci = (ub & 2u) ? fi : fi + 1u;
                         if (ci > 1u) {
                             w = xf_div_nz(w, (double)ci);
                             if (sp > 0u) {
@@ -955,6 +957,9 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
                     n += 1;
                     c_steps += 1;
                     Gpre = Gnx;
+                    // (moved to vector registers here, before the LDS writes below,
+                    // so that waiting for its scalar load never waits for them)
+                    asm volatile("" : "+v"(Gpre.m), "+v"(Gpre.e));
                     // ---- arrival: record into the running sums, eqn (4) ----
                     // (formed before the table insert, so that waiting for the
                     // record read never waits for the insert's LDS writes too)
