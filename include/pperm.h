@@ -268,6 +268,22 @@ int pperm_stats(pperm_ctx* ctx, pperm_seq_stats* total);
 /* Synchronise and return the first error a kernel raised (0 if none). */
 int pperm_sync(pperm_ctx* ctx);
 
+/* Checkpoint and resume between epochs.  Between a merge and the next run the
+ * whole future of a context is fixed by its configuration and its merged state
+ * (pooled sums, counts and tours, every sequence's tour counter and counters,
+ * group sums, observable sums), because the random numbers are counter-based.
+ * pperm_checkpoint_bytes gives the size of that state (O(n_max + N));
+ * pperm_checkpoint_save synchronises and copies it into a caller-owned host
+ * buffer; pperm_checkpoint_load writes it into a context created with the same
+ * problem (dim, n_max, N, seed, mode, stream_id and the result flags; the
+ * launch tuning fields may differ), after which every further call gives the
+ * same bits as on the saved context.  Errors: EINVAL (null pointers, short
+ * buffer, not a checkpoint, another problem), ESTATE (unmerged tours on the
+ * context), ERANGE / EOVERFLOW (a kernel error on the saved context), EDEVICE. */
+int pperm_checkpoint_bytes(const pperm_ctx* ctx, size_t* bytes);
+int pperm_checkpoint_save(pperm_ctx* ctx, void* host_buf, size_t bytes);
+int pperm_checkpoint_load(pperm_ctx* ctx, const void* host_buf, size_t bytes);
+
 /* Workspace layout and the launch shape the library chose. */
 int pperm_layout_of(const pperm_ctx* ctx, pperm_layout* out);
 int pperm_launch_shape(const pperm_ctx* ctx, uint32_t* walks_per_wave, uint32_t* hash_slots,

@@ -88,6 +88,9 @@ SIGNATURES = {
     "pperm_estimates": (_int, [_vp, _c.POINTER(_c.c_double), _c.POINTER(_u64), _c.POINTER(_u64), _sz]),
     "pperm_error_estimate": (_int, [_vp, _c.POINTER(_c.c_double), _c.POINTER(_c.c_double)]),
     "pperm_observable_r2": (_int, [_vp, _c.POINTER(_c.c_double), _sz]),
+    "pperm_checkpoint_bytes": (_int, [_vp, _c.POINTER(_sz)]),
+    "pperm_checkpoint_save": (_int, [_vp, _vp, _sz]),
+    "pperm_checkpoint_load": (_int, [_vp, _vp, _sz]),
     "pperm_sequence_stats": (_int, [_vp, _c.POINTER(SeqStats), _sz]),
     "pperm_stats": (_int, [_vp, _c.POINTER(SeqStats)]),
     "pperm_sync": (_int, [_vp]),

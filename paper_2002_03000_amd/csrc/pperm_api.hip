@@ -1133,6 +1133,115 @@ int pperm_sync(pperm_ctx* x) {
     return check_device_errors(x);
 }
 
+// ---- checkpoint / resume -----------------------------------------------------
+namespace {
+
+constexpr uint64_t kCkptMagic = 0x314B43504D524550ull;   // "PERMPCK1", little endian
+constexpr uint32_t kCkptVersion = 1;
+
+struct CkptHeader {
+    uint64_t magic;
+    uint32_t version;
+    uint32_t sections;
+    pperm_config cfg;
+    uint64_t merged_tours;
+    uint64_t payload_bytes;
+};
+
+// The merged state of a context as (workspace offset, bytes) sections, in
+// checkpoint order.  Per-sequence epoch sums and tour counts are not part of
+// it: they are zero between a merge and the next run.
+int ckpt_sections(const pperm_ctx* x, uint64_t off[8], uint64_t len[8]) {
+    const uint64_t N = x->cfg.n_sequences;
+    const uint64_t row = x->lay.row;
+    const uint64_t g = (x->cfg.mode == PPERM_INDEPENDENT) ? N : 1;
+    int k = 0;
+    off[k] = x->lay.G;      len[k++] = g * row * sizeof(SumRec);
+    off[k] = x->lay.HG;     len[k++] = g * row * 8;
+    off[k] = x->lay.MG;     len[k++] = g * 8;
+    off[k] = x->lay.t;      len[k++] = N * 8;
+    off[k] = x->lay.stats;  len[k++] = N * STATS_WORDS * 8;
+    off[k] = x->lay.groups; len[k++] = GROUPS * (sizeof(SumRec) + 8);
+    if (x->cfg.flags & PPERM_FLAG_OBSERVABLES) {
+        off[k] = x->lay.obs_G;
+        len[k++] = row * sizeof(SumRec);
+    }
+    return k;
+}
+
+bool same_problem(const pperm_config& a, const pperm_config& b) {
+    const uint32_t result_flags = PPERM_FLAG_GROUP_STATS | PPERM_FLAG_OBSERVABLES;
+    return a.dim == b.dim && a.n_max == b.n_max && a.n_sequences == b.n_sequences && a.seed == b.seed &&
+           a.mode == b.mode && a.stream_id == b.stream_id &&
+           (a.flags & result_flags) == (b.flags & result_flags);
+}
+
+}  // namespace
+
+int pperm_checkpoint_bytes(const pperm_ctx* x, size_t* bytes) {
+    if (!x || !bytes) return PPERM_EINVAL;
+    uint64_t off[8], len[8];
+    const int k = ckpt_sections(x, off, len);
+    uint64_t total = sizeof(CkptHeader);
+    for (int i = 0; i < k; ++i) total += len[i];
+    *bytes = (size_t)total;
+    return PPERM_OK;
+}
+
+int pperm_checkpoint_save(pperm_ctx* x, void* host_buf, size_t bytes) {
+    if (!x || !host_buf) return PPERM_EINVAL;
+    size_t need = 0;
+    pperm_checkpoint_bytes(x, &need);
+    if (bytes < need) return PPERM_EINVAL;
+    if (x->open_tours != 0) return PPERM_ESTATE;
+    int rc = check_device_errors(x);
+    if (rc) return rc;
+    uint64_t off[8], len[8];
+    const int k = ckpt_sections(x, off, len);
+    CkptHeader h;
+    memset(&h, 0, sizeof(h));
+    h.magic = kCkptMagic;
+    h.version = kCkptVersion;
+    h.sections = (uint32_t)k;
+    h.cfg = x->cfg;
+    h.merged_tours = x->merged_tours;
+    h.payload_bytes = need - sizeof(CkptHeader);
+    unsigned char* dst = static_cast<unsigned char*>(host_buf);
+    memcpy(dst, &h, sizeof(h));
+    dst += sizeof(h);
+    for (int i = 0; i < k; ++i) {
+        HIP_TRY(hipMemcpyAsync(dst, x->ws + off[i], len[i], hipMemcpyDeviceToHost, x->stream));
+        dst += len[i];
+    }
+    HIP_TRY(hipStreamSynchronize(x->stream));
+    return PPERM_OK;
+}
+
+int pperm_checkpoint_load(pperm_ctx* x, const void* host_buf, size_t bytes) {
+    if (!x || !host_buf || bytes < sizeof(CkptHeader)) return PPERM_EINVAL;
+    CkptHeader h;
+    memcpy(&h, host_buf, sizeof(h));
+    if (h.magic != kCkptMagic || h.version != kCkptVersion) return PPERM_EINVAL;
+    if (!same_problem(h.cfg, x->cfg)) return PPERM_EINVAL;
+    size_t need = 0;
+    pperm_checkpoint_bytes(x, &need);
+    uint64_t off[8], len[8];
+    const int k = ckpt_sections(x, off, len);
+    if (bytes < need || h.payload_bytes != need - sizeof(CkptHeader) || h.sections != (uint32_t)k)
+        return PPERM_EINVAL;
+    if (x->open_tours != 0) return PPERM_ESTATE;
+    int rc = check_device_errors(x);
+    if (rc) return rc;
+    const unsigned char* src = static_cast<const unsigned char*>(host_buf) + sizeof(h);
+    for (int i = 0; i < k; ++i) {
+        HIP_TRY(hipMemcpyAsync(x->ws + off[i], src, len[i], hipMemcpyHostToDevice, x->stream));
+        src += len[i];
+    }
+    HIP_TRY(hipStreamSynchronize(x->stream));
+    x->merged_tours = h.merged_tours;
+    return PPERM_OK;
+}
+
 int pperm_layout_of(const pperm_ctx* x, pperm_layout* out) {
     if (!x || !out) return PPERM_EINVAL;
     *out = x->lay;

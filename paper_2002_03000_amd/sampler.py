@@ -98,6 +98,19 @@ class ParallelFlatPERM:
                                                  self.n_max + 1), "pperm_observable_r2")
         return out
 
+    def checkpoint(self):
+        """The merged state as bytes (between a merge and the next run)."""
+        n = ctypes.c_size_t()
+        _abi.check(self._lib.pperm_checkpoint_bytes(self._ctx, ctypes.byref(n)), "pperm_checkpoint_bytes")
+        buf = ctypes.create_string_buffer(n.value)
+        _abi.check(self._lib.pperm_checkpoint_save(self._ctx, buf, n.value), "pperm_checkpoint_save")
+        return buf.raw
+
+    def restore(self, blob):
+        """Continue from a checkpoint of the same problem (any launch shape)."""
+        buf = ctypes.create_string_buffer(bytes(blob), len(blob))
+        _abi.check(self._lib.pperm_checkpoint_load(self._ctx, buf, len(blob)), "pperm_checkpoint_load")
+
     def sync(self):
         _abi.check(self._lib.pperm_sync(self._ctx), "pperm_sync")
 
