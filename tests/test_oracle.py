@@ -431,3 +431,29 @@ def test_observables_do_not_change_the_walks():
             o.run_tours(T)
             o.merge_epoch()
     assert np.array_equal(a.G["m"], b.G["m"]) and np.array_equal(a.stats["digest"], b.stats["digest"])
+
+
+def test_algorithm_1_sequences_do_not_interact():
+    # Algorithm 1 (no sharing): sequence s of an N-sequence run is the same run
+    # whatever N is, and sequence 0 is plain flatPERM with one sequence
+    sched = (1, 1, 2, 4, 8)
+    runs = {}
+    for N in (1, 3, 8):
+        o = oracle.Oracle(2, 30, N, 4242, mode=oracle.MODE_INDEPENDENT)
+        for T in sched:
+            o.run_tours(T)
+            o.merge_epoch()
+        runs[N] = o
+    plain = oracle.Oracle(2, 30, 1, 4242)
+    for T in sched:
+        plain.run_tours(T)
+        plain.merge_epoch()
+    for s in range(3):
+        for f in ("m", "e"):
+            assert np.array_equal(runs[3].G[f][s], runs[8].G[f][s])
+        assert np.array_equal(runs[3].HG[s], runs[8].HG[s])
+        assert np.array_equal(runs[3].stats["digest"][s], runs[8].stats["digest"][s])
+    for f in ("m", "e"):
+        assert np.array_equal(runs[8].G[f][0], runs[1].G[f][0])
+        assert np.array_equal(runs[1].G[f][0], plain.G[f])
+    assert np.array_equal(runs[1].HG[0], plain.HG)
