@@ -766,6 +766,13 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
         if constexpr (OBS) {
             for (uint32_t i = (uint32_t)lane; i <= n_max; i += 64u) LRs[i] = load_global(P.LR + rb0 + i);
         }
+    } else if (fresh) {
+        // the sums live in the global row: an epoch that starts here clears it
+        const SumRec z = {0.0, 0, 0u};
+        for (uint32_t i = (uint32_t)lane; i <= n_max; i += 64u) store_global(Lrow + i, z);
+        if constexpr (OBS) {
+            for (uint32_t i = (uint32_t)lane; i <= n_max; i += 64u) store_global(P.LR + rb0 + i, z);
+        }
     }
     wave_fence();
     SumRec rec0 = rec_ld(Ls);
