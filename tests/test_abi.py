@@ -134,3 +134,25 @@ def test_long_walk_limits(dim, n_max, ok):
     # slot ids must still fit in one workgroup's 160 KiB of LDS
     rc, n = _ws(_cfg(dim=dim, n_max=n_max, n_sequences=256))
     assert (rc == 0) == ok
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    # the product path has no CPU fallback: with the library absent, loading it
+    # raises instead of computing anything elsewhere
+    import subprocess
+    import sys
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "from paper_2002_03000_amd import _abi\n"
+        "_abi.LIB_PATH = %r\n"
+        "_abi._LIB = None\n"
+        "try:\n"
+        "    _abi.load()\n"
+        "except ImportError as e:\n"
+        "    print('raised', e)\n"
+        "else:\n"
+        "    print('loaded')\n"
+    ) % (str(__import__("pathlib").Path(__file__).resolve().parents[1]), str(tmp_path / "libpperm.so"))
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    assert out.stdout.startswith("raised"), out.stdout + out.stderr
+    assert "no CPU fallback" in out.stdout
