@@ -39,6 +39,7 @@ extern "C" {
 #define PPERM_ESTATE     -4   /* call out of order (e.g. estimates before any merge)  */
 #define PPERM_ERANGE     -5   /* a scaled weight left the normal FP64 range           */
 #define PPERM_EOVERFLOW  -6   /* step cap hit, or a tour/copy counter would overflow  */
+#define PPERM_EINCOMPLETE -7  /* a chained launch ended before all of its epochs ran  */
 
 /* ---- modes ------------------------------------------------------------------ */
 /* PPERM_SHARED: Algorithm 2 (Sec. 3, Fig. 1 right).  All sequences compare their
@@ -77,7 +78,7 @@ typedef struct pperm_config {
 
 /* Keep, beside every weight sum, the sum of W * R^2 over the same samples
  * (R^2: squared end-to-end distance of the walk), merged like the weights, for
- * the ratio estimator of eqn (42MC) (pperm_observable_r2).  Needs one walk per
+ * the ratio estimator of eqn (5) (pperm_observable_r2).  Needs one walk per
  * wavefront and PPERM_SHARED or PPERM_ROSENBLUTH mode; such contexts run
  * through pperm_run_tours / pperm_merge_epoch (and their graphs) only.  The
  * walks themselves, and every other result, are unchanged. */
@@ -135,7 +136,11 @@ typedef struct pperm_ctx pperm_ctx;
  * (used for admission by memory footprint).  *bytes receives the size. */
 int pperm_workspace_bytes(const pperm_config* cfg, size_t* bytes);
 
-/* Create a context.  cfg is copied.  d_workspace (>= pperm_workspace_bytes,
+/* Create a context: one instance of the problem the paper poses -- estimate
+ * c_n for n <= n_max on the d-dimensional hypercubic lattice (Sec. 1) with N
+ * flatPERM sequences sharing their running averages (Algorithm 2, Sec. 3 and
+ * Fig. 1), or kept apart (Algorithm 1) -- with every sum zero and no tour run.
+ * cfg is copied.  d_workspace (>= pperm_workspace_bytes,
  * 256-byte aligned) is caller-owned device memory that must outlive the
  * context; the library zero-initialises its state on `hip_stream` (a
  * hipStream_t, or NULL for the default stream).  *out receives the
@@ -152,9 +157,14 @@ int pperm_create(const pperm_config* cfg, void* d_workspace, size_t bytes,
  * 2^32 - 1), EDEVICE. */
 int pperm_run_tours(pperm_ctx* ctx, uint32_t tours_per_sequence);
 
-/* Close the epoch: fold every sequence's sums into the pooled sums with an
- * aligned pairwise tree over sequences (deterministic), then zero them.
- * Asynchronous. */
+/* Close the epoch: the pooling of Algorithm 2 (Sec. 3, Fig. 1 right), in
+ * which all sequences' weight sums and tour counts form one running average.
+ * Every sequence's sums of the epoch are added into the pooled sums G_n with
+ * an aligned pairwise tree over sequences (deterministic; padded with zeros
+ * to a power of two), its sample counts into HG_n and its tours into M, and
+ * then zeroed.  In PPERM_INDEPENDENT mode (Algorithm 1, Fig. 1 left) each
+ * sequence's sums go into its own pooled sums instead.  Asynchronous.
+ * Errors: EINVAL (null context), EDEVICE. */
 int pperm_merge_epoch(pperm_ctx* ctx);
 
 /* Device bytes of the scratch a batched launch of `count` problems needs. */
@@ -196,7 +206,11 @@ int pperm_job_workspace_bytes(pperm_ctx* const* ctxs, const uint32_t* epochs, si
  * merge, exactly as the calls pperm_run_tours(schedules[i][e]) and
  * pperm_merge_epoch would (Algorithm 2, Sec. 3; same bits).  Each problem
  * moves to its next epoch as soon as its own merge is done: sequences merge
- * into the aligned pairwise tree as they finish, on the device.  Problems run
+ * into the aligned pairwise tree as they finish, on the device.  A problem
+ * one of whose sequences hits its step cap stops after that epoch (its context
+ * then reports EOVERFLOW); the other problems run on.  After the launch every
+ * context whose epochs did not all run for another reason is flagged
+ * (pperm_estimates / pperm_sync then return EINCOMPLETE).  Problems run
  * in up to four LDS classes, one persistent launch each on library streams
  * forked from and joined into hip_stream (NULL: the default stream), which
  * must be ordered after all earlier work of the contexts.  d_workspace:
@@ -217,11 +231,22 @@ typedef struct pperm_job_limits {
     uint64_t tour_cap;
 } pperm_job_limits;
 
+/* What a chained launch (pperm_run_job or pperm_run_job_sliced) reported,
+ * read from its workspace after it ran (synchronises hip_stream). */
+typedef struct pperm_job_report_t {
+    uint32_t problems_finished;   /* problems that ran or stopped their whole schedule  */
+    uint32_t items_run;           /* (problem, epoch, sequence) items completed          */
+    uint32_t problems_failed;     /* problems stopped by a sequence's step cap           */
+    uint32_t waves_left_idle;     /* waves that left after 120 s without any progress    */
+    uint32_t problems_incomplete; /* problems whose epochs did not all run (pperm_run_job) */
+} pperm_job_report_t;
+int pperm_job_report(const void* d_workspace, size_t bytes, void* hip_stream, pperm_job_report_t* out);
+
 /* pperm_run_job with, per problem, the stop rule of limits[i] (NULL: none)
  * evaluated on the device after every merge, and a time slice: after slice_us
  * microseconds (0: none) no epoch starts, the epochs under way finish.  The
  * call synchronises and writes epochs_done[i] (epochs run and merged), stop[i]
- * (0, 1 target, 2 cap; may be NULL) and rel_err[i] (the estimate after the
+ * (0, 1 target, 2 tour cap, 3 step cap; may be NULL) and rel_err[i] (the estimate after the
  * last merge, +inf when undefined or with no stop rule; may be NULL).  A
  * problem's result is the same however its epochs are split over calls. */
 int pperm_run_job_sliced(pperm_ctx* const* ctxs, const uint32_t* const* schedules, const uint32_t* epochs,
@@ -239,6 +264,15 @@ int pperm_run_job_sliced(pperm_ctx* const* ctxs, const uint32_t* const* schedule
  * ERANGE / EOVERFLOW (raised by a kernel since the last check), EDEVICE. */
 int pperm_estimates(pperm_ctx* ctx, double* log_cn, uint64_t* hist, uint64_t* tours, size_t len);
 
+/* Algorithm 1 only (PPERM_INDEPENDENT): synchronise and write each sequence's
+ * own estimate -- eqn (4) for that sequence alone, its pooled weight sum over
+ * its own tours -- as log_cn[s * (n_max + 1) + n] (-inf where the sequence has
+ * no sample at n), the inputs of eqn (7) and of the geometric combination.
+ * log_cn: caller-owned host buffer of len >= N * (n_max + 1) entries.
+ * Errors: EINVAL (other modes, short buffer), ESTATE (a sequence with no
+ * merged tour), ERANGE / EOVERFLOW / EINCOMPLETE, EDEVICE. */
+int pperm_sequence_estimates(pperm_ctx* ctx, double* log_cn, size_t len);
+
 /* Synchronise and estimate the relative error of the estimate of c_{n_max}
  * from the 16 sequence groups (needs PPERM_FLAG_GROUP_STATS).  Each group k has
  * the cumulative sum A_k of the weights its sequences recorded at n_max (added
@@ -250,7 +284,7 @@ int pperm_estimates(pperm_ctx* ctx, double* log_cn, uint64_t* hist, uint64_t* to
  * may be NULL) receives log g_k.  Errors: EINVAL (flag not set), EDEVICE. */
 int pperm_error_estimate(pperm_ctx* ctx, double* rel_err, double* log_groups);
 
-/* Synchronise and read the ratio estimator of eqn (42MC) for O = R^2, the mean
+/* Synchronise and read the ratio estimator of eqn (5) for O = R^2, the mean
  * squared end-to-end distance of walks of length n under the uniform
  * distribution: out[n] = (pooled sum of W * R^2) / (pooled sum of W), from the
  * merged epochs, NaN where no sample reached n (out[0] = 0).  out: caller-owned

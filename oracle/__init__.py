@@ -270,7 +270,7 @@ class Oracle:
         return math.sqrt(ss / (GROUPS - 1)) / (4.0 * mean)
 
     def observable_r2(self):
-        """<R^2_n> by the ratio estimator of eqn (42MC) (shared mode), NaN where no sample."""
+        """<R^2_n> by the ratio estimator of eqn (5) (shared mode), NaN where no sample."""
         out = np.zeros(self.n_max + 1)
         lib().orc_observable_r2(self.n_max, self.G.ctypes.data, self.GR.ctypes.data, _ptr(out, ctypes.c_double))
         return out

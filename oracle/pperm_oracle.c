@@ -401,7 +401,7 @@ static double orc_uniform53(const uint32_t B[4])
 /*           the sequence's own; unused for the Rosenbluth mode)             */
 /*   L, H  : this sequence's sums of the current epoch (length n_max + 1)     */
 /*   LR    : this sequence's sums of W * R^2 (squared end-to-end distance),   */
-/*           the numerator of the ratio estimator, eqn (42MC); NULL: none     */
+/*           the numerator of the ratio estimator, eqn (5); NULL: none     */
 /*   m     : this sequence's tours in the current epoch                      */
 /*   t     : this sequence's global tour counter                             */
 /* Returns 0, or 1 if the step cap stopped the sequence.                    */
@@ -634,7 +634,7 @@ void orc_group_sums(const orc_params* P, int64_t N, const orc_xf* L, const uint3
     }
 }
 
-/* Ratio estimator (eqn (42MC)) of the mean squared end-to-end distance:
+/* Ratio estimator (eqn (5)) of the mean squared end-to-end distance:
  * <R^2>_n = (sum of W R^2) / (sum of W) at each length, NaN where no sample. */
 void orc_observable_r2(int64_t n_max, const orc_xf* G, const orc_xf* GR, double* out)
 {

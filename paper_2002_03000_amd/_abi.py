@@ -20,7 +20,7 @@ GROUPS = 16
 JOB_QUEUED, JOB_ACTIVE, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
 
 ERRORS = {0: "PPERM_OK", -1: "PPERM_EINVAL", -2: "PPERM_ENOMEM", -3: "PPERM_EDEVICE",
-          -4: "PPERM_ESTATE", -5: "PPERM_ERANGE", -6: "PPERM_EOVERFLOW"}
+          -4: "PPERM_ESTATE", -5: "PPERM_ERANGE", -6: "PPERM_EOVERFLOW", -7: "PPERM_EINCOMPLETE"}
 
 
 class Config(ctypes.Structure):
@@ -60,6 +60,20 @@ class JobLimits(ctypes.Structure):
     _fields_ = [("target_rel_err", ctypes.c_double), ("tour_cap", ctypes.c_uint64)]
 
 
+class JobReport(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_uint32) for f in ("problems_finished", "items_run", "problems_failed",
+                                                "waves_left_idle", "problems_incomplete")]
+
+
+class ProbeResult(ctypes.Structure):
+    _fields_ = [("valu_lane_ops_per_s", ctypes.c_double), ("lds_bytes_per_s", ctypes.c_double),
+                ("l2_bytes_per_s", ctypes.c_double), ("valu_ms", ctypes.c_double), ("lds_ms", ctypes.c_double),
+                ("l2_ms", ctypes.c_double), ("compute_units", ctypes.c_uint32), ("l2_buffer_bytes", ctypes.c_uint32)]
+
+
+PROBE_BUFFER_BYTES = 1 << 20
+
+
 class JobInfo(ctypes.Structure):
     _fields_ = [("state", ctypes.c_uint32), ("error", ctypes.c_int32),
                 ("epochs", ctypes.c_uint32), ("stop", ctypes.c_uint32),
@@ -85,7 +99,9 @@ SIGNATURES = {
     "pperm_run_job_sliced": (_int, [_c.POINTER(_vp), _c.POINTER(_c.POINTER(_u32)), _c.POINTER(_u32), _sz, _vp, _sz,
                                     _vp, _c.POINTER(JobLimits), _u32, _c.POINTER(_u32), _c.POINTER(_u32),
                                     _c.POINTER(_c.c_double)]),
+    "pperm_job_report": (_int, [_vp, _sz, _vp, _c.POINTER(JobReport)]),
     "pperm_estimates": (_int, [_vp, _c.POINTER(_c.c_double), _c.POINTER(_u64), _c.POINTER(_u64), _sz]),
+    "pperm_sequence_estimates": (_int, [_vp, _c.POINTER(_c.c_double), _sz]),
     "pperm_error_estimate": (_int, [_vp, _c.POINTER(_c.c_double), _c.POINTER(_c.c_double)]),
     "pperm_observable_r2": (_int, [_vp, _c.POINTER(_c.c_double), _sz]),
     "pperm_checkpoint_bytes": (_int, [_vp, _c.POINTER(_sz)]),
@@ -107,6 +123,7 @@ SIGNATURES = {
     "pperm_server_counts": (_int, [_vp, _c.POINTER(_u32), _c.POINTER(_u32), _c.POINTER(_u64)]),
     "pperm_server_destroy": (_int, [_vp]),
     "pperm_pool_script": (_c.c_int64, [_u64, _c.POINTER(_c.c_int64), _sz, _c.POINTER(_c.c_int64)]),
+    "pperm_probe": (_int, [_vp, _sz, _vp, _c.POINTER(ProbeResult)]),
     "pperm_strerror": (_c.c_char_p, [_int]),
     "pperm_last_device_error": (_c.c_char_p, []),
 }

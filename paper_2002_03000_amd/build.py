@@ -12,8 +12,10 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("pperm_kernels.hip", "pperm_api.hip", "pperm_server.hip")]
-HEADERS = [os.path.join(HERE, "csrc", "pperm_internal.h"), os.path.join(ROOT, "include", "pperm.h")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("pperm_kernels.hip", "pperm_api.hip", "pperm_server.hip",
+                                                         "pperm_probe.hip")]
+HEADERS = [os.path.join(HERE, "csrc", "pperm_internal.h"), os.path.join(ROOT, "include", "pperm.h"),
+           os.path.join(ROOT, "include", "pperm_probe.h")]
 LIB = os.path.join(HERE, "libpperm.so")
 ARCH = os.environ.get("PPERM_OFFLOAD_ARCH", "gfx950")
 

@@ -199,6 +199,7 @@ int check_device_errors(pperm_ctx* x) {
     HIP_TRY(hipStreamSynchronize(x->stream));
     if (err & ERR_RANGE) x->sticky_error = PPERM_ERANGE;
     else if (err & ERR_CAP) x->sticky_error = PPERM_EOVERFLOW;
+    else if (err & ERR_INCOMPLETE) x->sticky_error = PPERM_EINCOMPLETE;
     return x->sticky_error;
 }
 
@@ -238,6 +239,7 @@ const char* pperm_strerror(int code) {
         case PPERM_ESTATE: return "call out of order";
         case PPERM_ERANGE: return "scaled weight out of range";
         case PPERM_EOVERFLOW: return "step cap or counter overflow";
+        case PPERM_EINCOMPLETE: return "a chained launch ended before all of its epochs ran";
         default: return "unknown error";
     }
 }
@@ -322,6 +324,7 @@ int pperm_create(const pperm_config* cfg, void* d_workspace, size_t bytes, void*
     d.lds_team_bytes = sh.lds_team_bytes;
     d.key0 = (uint32_t)cfg->seed;
     d.key1 = (uint32_t)(cfg->seed >> 32) ^ cfg->stream_id;
+    d.step_cap = cfg->step_cap;
     d.LR = (cfg->flags & PPERM_FLAG_OBSERVABLES) ? at<SumRec>(x, L.obs_L) : nullptr;
     x->desc_dev = reinterpret_cast<ProblemDesc*>(at<uint32_t>(x, L.ctrl) + CTRL_WORDS);
 
@@ -512,18 +515,22 @@ int pperm_batch_workspace_bytes(size_t count, size_t* bytes) {
     return PPERM_OK;
 }
 
-int pperm_run_batch(pperm_ctx* const* ctxs, size_t count, const uint32_t* tours_each,
-                    void* d_workspace, size_t bytes, void* hip_stream) {
-    if (!ctxs || !tours_each || !d_workspace || count == 0) return PPERM_EINVAL;
-    size_t need = 0;
-    pperm_batch_workspace_bytes(count, &need);
-    if (bytes < need || ((uintptr_t)d_workspace & 255u)) return PPERM_EINVAL;
-    hipStream_t stream = (hipStream_t)hip_stream;
-    int device = -1;
-    HIP_TRY(hipGetDevice(&device));
+namespace {
 
-    // validate and size every problem's share
+// A batched epoch step, planned on the host: the validated items, their LDS
+// classes (one persistent launch each) and the launch entries in class order.
+struct BatchClass { size_t begin, end; uint32_t lds; uint32_t total; };
+struct BatchPlan {
     std::vector<BatchItem> items;
+    std::vector<BatchClass> classes;
+    std::vector<LaunchEntry> entries;
+};
+
+int plan_batch(pperm_ctx* const* ctxs, size_t count, const uint32_t* tours_each, int device,
+               BatchPlan* plan) {
+    // validate and size every problem's share
+    std::vector<BatchItem>& items = plan->items;
+    items.clear();
     items.reserve(count);
     for (size_t i = 0; i < count; ++i) {
         pperm_ctx* x = ctxs[i];
@@ -542,6 +549,8 @@ int pperm_run_batch(pperm_ctx* const* ctxs, size_t count, const uint32_t* tours_
         items.push_back({x, tours_each[i], lds,
                          (double)N * tours_each[i] * (double)(x->cfg.n_max + 1)});
     }
+    plan->classes.clear();
+    plan->entries.clear();
     if (items.empty()) return PPERM_OK;
 
     // LDS size classes (a launch gives every wave the largest share of its class);
@@ -550,8 +559,7 @@ int pperm_run_batch(pperm_ctx* const* ctxs, size_t count, const uint32_t* tours_
         if (a.lds != b.lds) return a.lds < b.lds;
         return a.work > b.work;
     });
-    struct Class { size_t begin, end; uint32_t lds; uint32_t total; };
-    std::vector<Class> classes;
+    std::vector<BatchClass>& classes = plan->classes;
     for (size_t i = 0; i < items.size();) {
         uint32_t cls = 8192;
         while (cls < items[i].lds) cls <<= 1;
@@ -560,15 +568,14 @@ int pperm_run_batch(pperm_ctx* const* ctxs, size_t count, const uint32_t* tours_
         classes.push_back({i, j, 0, 0});
         i = j;
     }
-    if (classes.size() > (size_t)kBatchStreams) {
-        // fold the smallest classes together (their waves then take the larger share)
-        while (classes.size() > (size_t)kBatchStreams) {
-            classes[1].begin = classes[0].begin;
-            classes.erase(classes.begin());
-        }
+    // fold the smallest classes together (their waves then take the larger share)
+    while (classes.size() > (size_t)kBatchStreams) {
+        classes[1].begin = classes[0].begin;
+        classes.erase(classes.begin());
     }
-    std::vector<LaunchEntry> host(items.size());
-    for (Class& c : classes) {
+    std::vector<LaunchEntry>& host = plan->entries;
+    host.resize(items.size());
+    for (BatchClass& c : classes) {
         uint32_t first = 0, lds = 0;
         // the class's entries in LPT order (largest expected work first)
         std::sort(items.begin() + c.begin, items.begin() + c.end,
@@ -590,23 +597,24 @@ int pperm_run_batch(pperm_ctx* const* ctxs, size_t count, const uint32_t* tours_
         c.lds = lds;
         c.total = first;
     }
+    return PPERM_OK;
+}
 
-    std::lock_guard<std::mutex> lock(g_batch_mutex);
-    DeviceStreams* ds = nullptr;
-    int rc = batch_streams(device, &ds);
-    if (rc) return rc;
-    unsigned char* ws = (unsigned char*)d_workspace;
-    LaunchEntry* dev_entries = reinterpret_cast<LaunchEntry*>(ws);
-    uint32_t* queues = reinterpret_cast<uint32_t*>(ws + align_up(count * sizeof(LaunchEntry), 256));
-    HIP_TRY(hipMemcpyAsync(dev_entries, host.data(), host.size() * sizeof(LaunchEntry),
+// Enqueue a planned batch: copy its entries to dev_entries, clear the queue
+// words (four per class, by a kernel) and launch one persistent grid per class.
+// With ds the classes run concurrently on the library's streams (forked from
+// and joined into `stream`); without, one after another on `stream` itself.
+int launch_plan(const BatchPlan& plan, int device, LaunchEntry* dev_entries, uint32_t* queues,
+                hipStream_t stream, DeviceStreams* ds) {
+    const std::vector<BatchClass>& classes = plan.classes;
+    HIP_TRY(hipMemcpyAsync(dev_entries, plan.entries.data(), plan.entries.size() * sizeof(LaunchEntry),
                            hipMemcpyHostToDevice, stream));
-    HIP_TRY(launch_reset_ctrl(queues, stream));   // classes use queue words 0..3
-    for (size_t c = 1; c < classes.size(); ++c) HIP_TRY(launch_reset_ctrl(queues + 4 * c, stream));
-    HIP_TRY(hipEventRecord(ds->fork, stream));
+    for (size_t c = 0; c < classes.size(); ++c) HIP_TRY(launch_reset_ctrl(queues + 4 * c, stream));
+    if (ds) HIP_TRY(hipEventRecord(ds->fork, stream));
     int cus = 0;
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
     for (size_t c = 0; c < classes.size(); ++c) {
-        const Class& C = classes[c];
+        const BatchClass& C = classes[c];
         int per_cu = 0;
         HIP_TRY(batch_occupancy(C.lds, &per_cu));
         if (per_cu < 1) return PPERM_EINVAL;
@@ -615,17 +623,45 @@ int pperm_run_batch(pperm_ctx* const* ctxs, size_t count, const uint32_t* tours_
         BatchArgs b;
         memset(&b, 0, sizeof(b));
         b.entries = dev_entries + C.begin;
-        b.single = host[C.begin];
+        b.single = plan.entries[C.begin];
         b.count = (uint32_t)(C.end - C.begin);
         b.total_items = C.total;
         b.queue = queues + 4 * c;
-        HIP_TRY(hipStreamWaitEvent(ds->s[c], ds->fork, 0));
-        HIP_TRY(launch_batch(b, (uint32_t)wgs, C.lds, ds->s[c]));
-        HIP_TRY(hipEventRecord(ds->join[c], ds->s[c]));
+        hipStream_t s = stream;
+        if (ds) {
+            HIP_TRY(hipStreamWaitEvent(ds->s[c], ds->fork, 0));
+            s = ds->s[c];
+        }
+        HIP_TRY(launch_batch(b, (uint32_t)wgs, C.lds, s));
+        if (ds) HIP_TRY(hipEventRecord(ds->join[c], ds->s[c]));
     }
-    for (size_t c = 0; c < classes.size(); ++c) HIP_TRY(hipStreamWaitEvent(stream, ds->join[c], 0));
-    for (const BatchItem& it : items) it.ctx->open_tours += it.tours;
+    if (ds)
+        for (size_t c = 0; c < classes.size(); ++c) HIP_TRY(hipStreamWaitEvent(stream, ds->join[c], 0));
+    for (const BatchItem& it : plan.items) it.ctx->open_tours += it.tours;
     return PPERM_OK;
+}
+
+}  // namespace
+
+int pperm_run_batch(pperm_ctx* const* ctxs, size_t count, const uint32_t* tours_each,
+                    void* d_workspace, size_t bytes, void* hip_stream) {
+    if (!ctxs || !tours_each || !d_workspace || count == 0) return PPERM_EINVAL;
+    size_t need = 0;
+    pperm_batch_workspace_bytes(count, &need);
+    if (bytes < need || ((uintptr_t)d_workspace & 255u)) return PPERM_EINVAL;
+    int device = -1;
+    HIP_TRY(hipGetDevice(&device));
+    BatchPlan plan;
+    int rc = plan_batch(ctxs, count, tours_each, device, &plan);
+    if (rc || plan.items.empty()) return rc;
+    std::lock_guard<std::mutex> lock(g_batch_mutex);
+    DeviceStreams* ds = nullptr;
+    rc = batch_streams(device, &ds);
+    if (rc) return rc;
+    unsigned char* ws = (unsigned char*)d_workspace;
+    return launch_plan(plan, device, reinterpret_cast<LaunchEntry*>(ws),
+                       reinterpret_cast<uint32_t*>(ws + align_up(count * sizeof(LaunchEntry), 256)),
+                       (hipStream_t)hip_stream, ds);
 }
 
 // ---- one epoch as a captured HIP graph -------------------------------------------
@@ -731,10 +767,10 @@ void job_layout(pperm_ctx* const* ctxs, const uint32_t* epochs, size_t count, Jo
         off = align_up(off + (bytes ? bytes : 1), 256);
         return o;
     };
+    L->counters = take(JOB_COUNTER_WORDS * 4);        // first: pperm_job_report reads it
     L->probs = take(count * sizeof(JobProblem));
     L->state = take(count * sizeof(JobState));
     L->order = take(count * 4);
-    L->counters = take(JOB_COUNTER_WORDS * 4);
     L->results = take(count * 4 * 4);
     L->sched.assign(count, 0);
     L->gver.assign(count, 0);
@@ -941,6 +977,16 @@ int run_job_impl(pperm_ctx* const* ctxs, const uint32_t* const* schedules, const
         HIP_TRY(hipEventRecord(ds->join[c], ds->s[c]));
     }
     for (uint32_t c = 0; c < K; ++c) HIP_TRY(hipStreamWaitEvent(stream, ds->join[c], 0));
+    if (slice_us == 0u && !limits) {
+        // every epoch given must have run: flag any context whose did not
+        JobArgs a;
+        memset(&a, 0, sizeof(a));
+        a.probs = reinterpret_cast<const JobProblem*>(ws + L.probs);
+        a.order = reinterpret_cast<const uint32_t*>(ws + L.order);
+        a.counters = reinterpret_cast<uint32_t*>(ws + L.counters);
+        a.count = (uint32_t)order.size();
+        HIP_TRY(launch_job_check(a, stream));
+    }
     // the state a merge leaves: sums of the open epoch zero
     for (size_t i = 0; i < count; ++i) {
         pperm_ctx* x = ctxs[i];
@@ -992,6 +1038,19 @@ int pperm_run_job_sliced(pperm_ctx* const* ctxs, const uint32_t* const* schedule
             rel_err[i] = done ? r : INFINITY;
         }
     }
+    return PPERM_OK;
+}
+
+int pperm_job_report(const void* d_workspace, size_t bytes, void* hip_stream, pperm_job_report_t* out) {
+    if (!d_workspace || !out || bytes < JOB_COUNTER_WORDS * 4) return PPERM_EINVAL;
+    uint32_t c[JOB_COUNTER_WORDS];
+    HIP_TRY(hipMemcpyAsync(c, d_workspace, sizeof(c), hipMemcpyDeviceToHost, (hipStream_t)hip_stream));
+    HIP_TRY(hipStreamSynchronize((hipStream_t)hip_stream));
+    out->problems_finished = c[JOB_FINISHED0] + c[JOB_FINISHED0 + 1] + c[JOB_FINISHED0 + 2] + c[JOB_FINISHED0 + 3];
+    out->items_run = c[JOB_PROGRESS];
+    out->problems_failed = c[JOB_FAILED];
+    out->waves_left_idle = c[JOB_BACKSTOP];
+    out->problems_incomplete = c[JOB_INCOMPLETE];
     return PPERM_OK;
 }
 
@@ -1054,6 +1113,30 @@ int pperm_estimates(pperm_ctx* x, double* log_cn, uint64_t* hist, uint64_t* tour
     return PPERM_OK;
 }
 
+int pperm_sequence_estimates(pperm_ctx* x, double* log_cn, size_t len) {
+    if (!x || !log_cn) return PPERM_EINVAL;
+    if (x->cfg.mode != PPERM_INDEPENDENT) return PPERM_EINVAL;
+    const uint32_t N = x->cfg.n_sequences, n1 = x->cfg.n_max + 1, row = x->lay.row;
+    if (len < (size_t)N * n1) return PPERM_EINVAL;
+    int rc = check_device_errors(x);
+    if (rc) return rc;
+    std::vector<SumRec> G((size_t)N * row);
+    std::vector<uint64_t> MG(N);
+    HIP_TRY(hipMemcpy(G.data(), at<SumRec>(x, x->lay.G), G.size() * sizeof(SumRec), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(MG.data(), at<uint64_t>(x, x->lay.MG), MG.size() * 8, hipMemcpyDeviceToHost));
+    const double ln2 = 0.69314718055994530942;
+    for (uint32_t s = 0; s < N; ++s) {
+        if (MG[s] == 0) return PPERM_ESTATE;
+        const double lm = log((double)MG[s]);
+        // eqn (4) for sequence s alone: its weight sum over its own tours
+        for (uint32_t n = 0; n < n1; ++n) {
+            const SumRec& g = G[(size_t)s * row + n];
+            log_cn[(size_t)s * n1 + n] = (g.m == 0.0) ? -INFINITY : log(g.m) + g.e * ln2 - lm;
+        }
+    }
+    return PPERM_OK;
+}
+
 int pperm_error_estimate(pperm_ctx* x, double* rel_err, double* log_groups) {
     if (!x || !rel_err) return PPERM_EINVAL;
     if (!(x->cfg.flags & PPERM_FLAG_GROUP_STATS)) return PPERM_EINVAL;
@@ -1092,7 +1175,7 @@ int pperm_observable_r2(pperm_ctx* x, double* out, size_t len) {
     HIP_TRY(hipMemcpy(G.data(), at<SumRec>(x, x->lay.G), n1 * sizeof(SumRec), hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(GR.data(), at<SumRec>(x, x->lay.obs_G), n1 * sizeof(SumRec),
                       hipMemcpyDeviceToHost));
-    // eqn (42MC): the pooled sum of W * R^2 over the pooled sum of W (the
+    // eqn (5): the pooled sum of W * R^2 over the pooled sum of W (the
     // tour counts of numerator and denominator cancel)
     for (uint32_t n = 0; n < n1; ++n)
         out[n] = (G[n].m == 0.0) ? NAN : ldexp(GR[n].m / G[n].m, GR[n].e - G[n].e);

@@ -8,8 +8,10 @@ typedef struct pperm_config pperm_config;
 
 namespace pperm {
 
-// Error bits a kernel may raise in ctrl[1].
-enum : uint32_t { ERR_CAP = 1u, ERR_RANGE = 2u };
+// Error bits a kernel may raise in ctrl[1]: the step cap stopped a sequence; a
+// weight left the exponent range; a chained launch ended before every epoch
+// it was given for the context had run.
+enum : uint32_t { ERR_CAP = 1u, ERR_RANGE = 2u, ERR_INCOMPLETE = 4u };
 
 // Exponents beyond this magnitude are reported as PPERM_ERANGE.
 constexpr int32_t EXP_LIMIT = 1 << 30;
@@ -87,7 +89,7 @@ struct ProblemDesc {
     uint32_t slots_log2;
     uint32_t lds_team_bytes;   // occupancy table + slot ids; the sums row follows
     uint32_t key0, key1;
-    uint32_t pad;
+    uint32_t step_cap;    // the configuration's step cap per sequence and call (0: default)
     SumRec* LR;           // [N][row] per-sequence sums of W * R^2, or nullptr
 };
 
@@ -153,15 +155,24 @@ struct JobProblem {
     uint64_t cap;             // stop once the pooled tours M reach this, 0: none
 };
 
-// Per-problem scheduling word: (epoch << 32) | sequences claimed in it; and
-// the tours of the epoch's finished sequences.
+// Per-problem scheduling word: (epoch << 32) | sequences claimed in it; the
+// tours of the epoch's finished sequences; and a flag raised when one of the
+// problem's sequences hit its step cap (the problem then stops after that
+// epoch).
 struct JobState {
     unsigned long long word;
     uint32_t msum;
-    uint32_t pad;
+    uint32_t failed;
 };
 
-enum : uint32_t { JOB_FINISHED0 = 0, JOB_PROGRESS = 4, JOB_ERROR = 5, JOB_CLOCK = 8, JOB_COUNTER_WORDS = 16 };
+// Counter words of a chained launch (at offset 0 of its workspace):
+// problems finished per LDS class, items completed, problems stopped by a
+// step cap, waves that left on the idle backstop, problems whose epochs did
+// not all run, and the slice's start time (two words).
+enum : uint32_t { JOB_FINISHED0 = 0, JOB_PROGRESS = 4, JOB_FAILED = 5, JOB_BACKSTOP = 6,
+                  JOB_INCOMPLETE = 7, JOB_CLOCK = 8, JOB_COUNTER_WORDS = 16 };
+// stop reasons a chained problem records: error target, tour cap, step cap
+enum : uint32_t { STOP_TARGET = 1, STOP_CAP = 2, STOP_FAILED = 3 };
 // records between consecutive per-epoch copies of the pooled sums (256 bytes)
 constexpr uint32_t JOB_GAP = 16;
 
@@ -178,6 +189,9 @@ struct JobArgs {
 };
 
 hipError_t launch_job(const JobArgs& a, uint32_t workgroups, uint32_t lds_bytes, hipStream_t s);
+// After a whole-schedule launch: flag the context of every problem whose
+// epochs did not all run (ERR_INCOMPLETE) and count them.
+hipError_t launch_job_check(const JobArgs& a, hipStream_t s);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t job_occupancy(uint32_t lds_bytes, int* blocks_per_cu);
 
@@ -188,6 +202,7 @@ bool config_long_walk(const pperm_config* c);
 hipError_t launch_batch(const BatchArgs& b, uint32_t workgroups, uint32_t lds_bytes, hipStream_t s,
                         bool observables = false, bool long_walk = false);
 hipError_t batch_occupancy(uint32_t lds_bytes, int* blocks_per_cu);
+
 hipError_t launch_merge_counts(const uint32_t* m, uint32_t N, uint64_t* MG, uint32_t* zero_m,
                                hipStream_t s);
 hipError_t launch_group_sums(const SumRec* L, const uint32_t* m, uint32_t N, uint32_t row,

@@ -664,15 +664,18 @@ __device__ __forceinline__ uint64_t fields_lanes(uint64_t hb) {
 // of one walk); run by one wavefront.  Gsrc: the pooled sums to read (the
 // problem's own, or an epoch's copy in a chained launch); fresh: the epoch
 // starts here, so the sequence's sums and tour count start from zero instead
-// of being read.  Returns the tours run.  Every value below is wave-uniform
+// of being read.  Returns the tours run, with bit 31 set if the step cap
+// stopped the sequence (WALK_ABORTED).  Every value below is wave-uniform
 // except where a lane index enters (scan windows, Philox counters, deletions).
 // A step issues its occupancy reads first, evaluates the prune/enrich
 // arithmetic while they are in flight, and only then resolves the scan.
 // OBS: also record W * R^2 (squared end-to-end distance) at every arrival
-// beside the weight, the numerator of the ratio estimator of eqn (42MC).
+// beside the weight, the numerator of the ratio estimator of eqn (5).
 // LONG: walks too long for the per-length sums to share LDS with the
 // occupancy table; the sums stay in the sequence's global row (read and
 // written in place) and LDS holds the table, the slot ids and the stack bottom.
+constexpr uint32_t WALK_ABORTED = 0x80000000u;
+
 template <int D, bool OBS = false, bool LONG = false>
 __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t tours, uint32_t cap,
                                                   uint32_t s, unsigned char* lds, const SumRec* Gsrc,
@@ -1055,7 +1058,7 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
     if (lane == ST_EVENTS || lane == ST_ENRICH || lane == ST_COPIES || lane == ST_PRUNES ||
         lane == ST_TRAPS)
         P.stats[(size_t)s * STATS_WORDS + lane] += cv;
-    return c_tours;
+    return c_tours | (abort ? WALK_ABORTED : 0u);
 }
 
 // Persistent launch over (problem, sequence) items of one or many problems:
@@ -1263,9 +1266,15 @@ __device__ void job_merge(const JobArgs& A, const JobProblem& J, const ProblemDe
         uint64_t* MG = const_cast<uint64_t*>(P.MG);
         const uint64_t M = MG[0] + msum;
         MG[0] = M;
+        // a problem one of whose sequences hit its step cap stops after this
+        // epoch (its context reports the overflow); the others run on
+        const bool failed =
+            __hip_atomic_load(&A.state[pi].failed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
         uint32_t stop = 0u;
-        if (J.stage != nullptr && J.target > 0.0 && rel <= J.target) stop = 1u;
-        else if (J.cap != 0u && M >= J.cap) stop = 2u;
+        if (failed) stop = STOP_FAILED;
+        else if (J.stage != nullptr && J.target > 0.0 && rel <= J.target) stop = STOP_TARGET;
+        else if (J.cap != 0u && M >= J.cap) stop = STOP_CAP;
+        if (failed) __hip_atomic_fetch_add(&A.counters[JOB_FAILED], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (J.result != nullptr) {
             J.result[0] = e + 1u;
             J.result[1] = stop;
@@ -1343,7 +1352,6 @@ __global__ void __launch_bounds__(64) job_kernel(JobArgs A) {
             // used up), so a wave that finds nothing may leave
             if (closed) break;
             if (job_finished(A) >= A.need) break;
-            if (__hip_atomic_load(&A.counters[JOB_ERROR], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
             const uint32_t prog =
                 __hip_atomic_load(&A.counters[JOB_PROGRESS], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const uint64_t now = __builtin_amdgcn_s_memrealtime();
@@ -1351,7 +1359,10 @@ __global__ void __launch_bounds__(64) job_kernel(JobArgs A) {
                 seen_progress = prog;
                 idle_since = now;
             } else if (now - idle_since > JOB_IDLE_TICKS) {
-                break;                                    // backstop: leave the rest to others
+                // backstop: leave the rest to others (counted, pperm_job_report)
+                if (lane == 0)
+                    __hip_atomic_fetch_add(&A.counters[JOB_BACKSTOP], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
             }
             __builtin_amdgcn_s_sleep(127);
             continue;
@@ -1364,16 +1375,34 @@ __global__ void __launch_bounds__(64) job_kernel(JobArgs A) {
         if (J.prio == 3u) __builtin_amdgcn_s_setprio(3);
         else if (J.prio == 2u) __builtin_amdgcn_s_setprio(2);
         else if (J.prio == 1u) __builtin_amdgcn_s_setprio(1);
-        uint64_t cap64 = 4096ull * tours * (P.n_max + 1ull);
+        // the context's step cap, or the watchdog default of pperm_run_tours
+        uint64_t cap64 = P.step_cap ? (uint64_t)P.step_cap : 4096ull * tours * (P.n_max + 1ull);
         const uint32_t cap = cap64 > (1ull << 31) ? (1u << 31) : (uint32_t)cap64;
         const SumRec* Gsrc = (e == 0u) ? P.G : J.gver + (size_t)(e - 1u) * (P.row + JOB_GAP);
-        const uint32_t ran = (P.dim == 2) ? walk_sequence<2>(P, tours, cap, s, lds, Gsrc, true)
-                                          : walk_sequence<3>(P, tours, cap, s, lds, Gsrc, true);
-        job_merge(A, J, P, pi, e, s, ran, lds);
+        const uint32_t rv = (P.dim == 2) ? walk_sequence<2>(P, tours, cap, s, lds, Gsrc, true)
+                                         : walk_sequence<3>(P, tours, cap, s, lds, Gsrc, true);
+        if ((rv & WALK_ABORTED) && lane == 0)
+            __hip_atomic_fetch_or(&A.state[pi].failed, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        job_merge(A, J, P, pi, e, s, rv & ~WALK_ABORTED, lds);
         __builtin_amdgcn_s_setprio(0);
         if (lane == 0)
             __hip_atomic_fetch_add(&A.counters[JOB_PROGRESS], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         idle_since = __builtin_amdgcn_s_memrealtime();
+    }
+}
+
+// After a whole-schedule launch: every problem must have merged all of its
+// epochs, or have stopped on a step cap (reported through its context
+// already).  Anything else -- the launch ended early -- is flagged on the
+// problem's context and counted.
+__global__ void __launch_bounds__(256) job_check_kernel(JobArgs A) {
+    for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < A.count; i += gridDim.x * 256u) {
+        const JobProblem& J = A.probs[A.order[i]];
+        const uint32_t done = J.result[0], stop = J.result[1];
+        if (done != J.epochs && stop != STOP_FAILED) {
+            atomicOr(&J.desc->ctrl[CTRL_ERR], ERR_INCOMPLETE);
+            atomicAdd(&A.counters[JOB_INCOMPLETE], 1u);
+        }
     }
 }
 
@@ -1589,6 +1618,12 @@ hipError_t launch_batch(const BatchArgs& b, uint32_t workgroups, uint32_t lds_by
 
 hipError_t launch_job(const JobArgs& a, uint32_t workgroups, uint32_t lds_bytes, hipStream_t s) {
     hipLaunchKernelGGL(job_kernel, dim3(workgroups), dim3(64), lds_bytes, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_job_check(const JobArgs& a, hipStream_t s) {
+    const uint32_t blocks = (a.count + 255u) / 256u;
+    hipLaunchKernelGGL(job_check_kernel, dim3(blocks ? blocks : 1u), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -1,0 +1,164 @@
+// Microbenchmarks of the three ceilings the growth kernel is reported against
+// (include/pperm_probe.h): 32-bit VALU issue, LDS read bandwidth and L2 read
+// bandwidth, each measured on the whole device with HIP events.
+//
+// Every probe fills the device (workgroups per CU sized for its resource) and
+// keeps its result live with a store that never happens in practice (the
+// condition depends on the data) into the first bytes of the caller's buffer.
+#include <hip/hip_runtime.h>
+#include <stdio.h>
+
+#include "pperm.h"
+#include "pperm_probe.h"
+
+namespace {
+
+constexpr uint32_t kValuIters = 8192;
+constexpr uint32_t kValuOpsPerIter = 16;     // 8 chains x (add, xor) per lane
+constexpr uint32_t kValuBlocksPerCU = 8;     // 8 waves per SIMD
+constexpr uint32_t kLdsEntries = 4096;       // 64 KiB of uint4 per workgroup
+constexpr uint32_t kLdsIters = 8192;
+constexpr uint32_t kLdsReadsPerIter = 4;
+constexpr uint32_t kLdsBlocksPerCU = 2;      // 2 x 64 KiB of the 160 KiB
+constexpr uint32_t kL2Bytes = 1u << 20;      // read by every workgroup, resident in each XCD's L2
+constexpr uint32_t kL2Passes = 4;
+constexpr uint32_t kL2BlocksPerCU = 4;
+static_assert(kL2Bytes <= PPERM_PROBE_BUFFER_BYTES, "the L2 probe reads the caller's buffer");
+
+__global__ void __launch_bounds__(256) valu_probe_kernel(uint32_t* sink, uint32_t k) {
+    uint32_t a0 = threadIdx.x, a1 = a0 + 1u, a2 = a0 + 2u, a3 = a0 + 3u;
+    uint32_t a4 = a0 + 4u, a5 = a0 + 5u, a6 = a0 + 6u, a7 = a0 + 7u;
+    for (uint32_t i = 0; i < kValuIters; ++i) {
+        // eight independent chains, so that issue and not latency bounds the loop
+        asm volatile(
+            "v_add_u32 %0, %0, %8\n\t"
+            "v_add_u32 %1, %1, %8\n\t"
+            "v_add_u32 %2, %2, %8\n\t"
+            "v_add_u32 %3, %3, %8\n\t"
+            "v_add_u32 %4, %4, %8\n\t"
+            "v_add_u32 %5, %5, %8\n\t"
+            "v_add_u32 %6, %6, %8\n\t"
+            "v_add_u32 %7, %7, %8\n\t"
+            "v_xor_b32 %0, %0, %8\n\t"
+            "v_xor_b32 %1, %1, %8\n\t"
+            "v_xor_b32 %2, %2, %8\n\t"
+            "v_xor_b32 %3, %3, %8\n\t"
+            "v_xor_b32 %4, %4, %8\n\t"
+            "v_xor_b32 %5, %5, %8\n\t"
+            "v_xor_b32 %6, %6, %8\n\t"
+            "v_xor_b32 %7, %7, %8"
+            : "+v"(a0), "+v"(a1), "+v"(a2), "+v"(a3), "+v"(a4), "+v"(a5), "+v"(a6), "+v"(a7)
+            : "v"(k));
+    }
+    const uint32_t x = a0 ^ a1 ^ a2 ^ a3 ^ a4 ^ a5 ^ a6 ^ a7;
+    if (x == 0x9E3779B9u) sink[threadIdx.x & 63u] = x;
+}
+
+__global__ void __launch_bounds__(256) lds_probe_kernel(uint32_t* sink, uint32_t k) {
+    __shared__ uint4 buf[kLdsEntries];
+    for (uint32_t i = threadIdx.x; i < kLdsEntries; i += 256u) buf[i] = make_uint4(i, i ^ k, i + k, i * 3u);
+    __syncthreads();
+    uint32_t acc0 = 0u, acc1 = 0u;
+    for (uint32_t it = 0; it < kLdsIters; ++it) {
+        // consecutive lanes read consecutive 16-byte entries (no bank
+        // conflicts); the base moves every iteration, the four reads are a
+        // quarter of the table apart (immediate offsets)
+        const uint32_t base = (threadIdx.x + it * 37u) & (kLdsEntries / kLdsReadsPerIter - 1u);
+#pragma unroll
+        for (uint32_t j = 0; j < kLdsReadsPerIter; ++j) {
+            const uint4 v = buf[base + j * (kLdsEntries / kLdsReadsPerIter)];
+            acc0 = acc0 ^ v.x ^ v.y;
+            acc1 = acc1 ^ v.z ^ v.w;
+        }
+    }
+    if ((acc0 ^ acc1) == 0x9E3779B9u) sink[threadIdx.x & 63u] = acc0;
+}
+
+__global__ void __launch_bounds__(256) l2_probe_kernel(const uint4* buf, uint32_t* sink) {
+    constexpr uint32_t n16 = kL2Bytes / 16u;
+    // every workgroup streams the whole buffer from its own starting point
+    // (far from its neighbours', so that the vector L1 rarely holds a line a
+    // workgroup is about to read); one wave reads 1 KiB per instruction
+    uint32_t i = ((blockIdx.x * 12289u) & (n16 - 1u) & ~255u) + threadIdx.x;
+    uint32_t acc0 = 0u, acc1 = 0u;
+    for (uint32_t p = 0; p < kL2Passes; ++p) {
+        for (uint32_t r = 0; r < n16 / 256u; ++r) {
+            const uint4 v = buf[i];
+            acc0 = acc0 ^ v.x ^ v.y;
+            acc1 = acc1 ^ v.z ^ v.w;
+            i = (i + 256u) & (n16 - 1u);
+        }
+    }
+    if ((acc0 ^ acc1) == 0x9E3779B9u) sink[threadIdx.x & 63u] = acc0;
+}
+
+char g_err[256];
+
+int fail(hipError_t e, const char* what) {
+    snprintf(g_err, sizeof(g_err), "%s: %s", what, hipGetErrorString(e));
+    return PPERM_EDEVICE;
+}
+
+#define PROBE_TRY(expr)                                  \
+    do {                                                 \
+        hipError_t e_ = (expr);                          \
+        if (e_ != hipSuccess) return fail(e_, #expr);    \
+    } while (0)
+
+// One untimed and one timed launch of `launch`; *ms receives the timed one.
+template <typename F>
+int timed(hipStream_t s, F launch, double* ms) {
+    hipEvent_t a, b;
+    PROBE_TRY(hipEventCreate(&a));
+    PROBE_TRY(hipEventCreate(&b));
+    launch();
+    PROBE_TRY(hipGetLastError());
+    PROBE_TRY(hipEventRecord(a, s));
+    launch();
+    PROBE_TRY(hipGetLastError());
+    PROBE_TRY(hipEventRecord(b, s));
+    PROBE_TRY(hipEventSynchronize(b));
+    float f = 0.0f;
+    PROBE_TRY(hipEventElapsedTime(&f, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    *ms = f;
+    return PPERM_OK;
+}
+
+}  // namespace
+
+extern "C" int pperm_probe(void* d_buffer, size_t bytes, void* hip_stream, pperm_probe_result* out) {
+    if (!d_buffer || !out || bytes < PPERM_PROBE_BUFFER_BYTES || ((uintptr_t)d_buffer & 255u)) return PPERM_EINVAL;
+    hipStream_t s = (hipStream_t)hip_stream;
+    int dev = -1, cus = 0;
+    PROBE_TRY(hipGetDevice(&dev));
+    PROBE_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    uint32_t* sink = static_cast<uint32_t*>(d_buffer);
+    // the L2 probe reads the whole MiB; a result store into its first 256
+    // bytes happens only when a checksum hits one fixed value
+    const uint4* l2buf = static_cast<const uint4*>(d_buffer);
+    const uint32_t ncu = (uint32_t)cus;
+    double ms = 0.0;
+    int rc = timed(s, [&] {
+        hipLaunchKernelGGL(valu_probe_kernel, dim3(ncu * kValuBlocksPerCU), dim3(256), 0, s, sink, 1u);
+    }, &ms);
+    if (rc) return rc;
+    out->valu_ms = ms;
+    out->valu_lane_ops_per_s = (double)ncu * kValuBlocksPerCU * 256.0 * kValuIters * kValuOpsPerIter / (ms * 1e-3);
+    rc = timed(s, [&] {
+        hipLaunchKernelGGL(lds_probe_kernel, dim3(ncu * kLdsBlocksPerCU), dim3(256), 0, s, sink, 1u);
+    }, &ms);
+    if (rc) return rc;
+    out->lds_ms = ms;
+    out->lds_bytes_per_s = (double)ncu * kLdsBlocksPerCU * 256.0 * kLdsIters * kLdsReadsPerIter * 16.0 / (ms * 1e-3);
+    rc = timed(s, [&] {
+        hipLaunchKernelGGL(l2_probe_kernel, dim3(ncu * kL2BlocksPerCU), dim3(256), 0, s, l2buf, sink);
+    }, &ms);
+    if (rc) return rc;
+    out->l2_ms = ms;
+    out->l2_bytes_per_s = (double)ncu * kL2BlocksPerCU * (double)kL2Bytes * kL2Passes / (ms * 1e-3);
+    out->compute_units = ncu;
+    out->l2_buffer_bytes = kL2Bytes;
+    return PPERM_OK;
+}

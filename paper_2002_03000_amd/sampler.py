@@ -76,10 +76,10 @@ class ParallelFlatPERM:
         if self.mode != "independent":
             raise ValueError("per-sequence estimates exist in independent mode only")
         n1 = self.n_max + 1
-        rec = self.records("G")[:, :n1]
-        MG = self.view("MG").cpu().numpy().view(np.uint64).astype(np.float64)
-        with np.errstate(divide="ignore"):
-            return np.log(rec["m"]) + rec["e"] * np.log(2.0) - np.log(MG)[:, None]
+        out = np.zeros(self.N * n1, dtype=np.float64)
+        _abi.check(self._lib.pperm_sequence_estimates(self._ctx, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                                      out.size), "pperm_sequence_estimates")
+        return out.reshape(self.N, n1)
 
     def error_estimate(self):
         """(relative error estimate of c_{n_max} from 16 sequence groups, log group estimates)."""
@@ -91,7 +91,7 @@ class ParallelFlatPERM:
         return rel.value, lg
 
     def observable_r2(self):
-        """<R^2_n>, the ratio estimator of eqn (42MC) for the squared end-to-end
+        """<R^2_n>, the ratio estimator of eqn (5) for the squared end-to-end
         distance, from the merged epochs (NaN where no sample reached n)."""
         out = np.zeros(self.n_max + 1, dtype=np.float64)
         _abi.check(self._lib.pperm_observable_r2(self._ctx, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
@@ -209,6 +209,31 @@ class Batch:
                                              self.workspace.numel(),
                                              ctypes.c_void_p(self.stream.cuda_stream)),
                    "pperm_run_batch")
+
+
+def probe(device=None, stream=None):
+    """The measured ceilings of the device (pperm_probe): 32-bit VALU lane-ops/s,
+    LDS bytes/s and L2 bytes/s, with the duration of each timed launch."""
+    lib = _abi.load()
+    device = torch.device(device if device is not None else "cuda")
+    res = _abi.ProbeResult()
+    with torch.cuda.device(device):
+        stream = stream if stream is not None else torch.cuda.current_stream(device)
+        buf = torch.empty(_abi.PROBE_BUFFER_BYTES, dtype=torch.uint8, device=device)
+        _abi.check(lib.pperm_probe(ctypes.c_void_p(buf.data_ptr()), buf.numel(), ctypes.c_void_p(stream.cuda_stream),
+                                   ctypes.byref(res)), "pperm_probe")
+    return {f: getattr(res, f) for f, _ in _abi.ProbeResult._fields_}
+
+
+def job_report(ws, stream=None):
+    """The counters a chained launch left in its workspace `ws` (pperm_job_report)."""
+    lib = _abi.load()
+    rep = _abi.JobReport()
+    with torch.cuda.device(ws.device):
+        stream = stream if stream is not None else torch.cuda.current_stream(ws.device)
+        _abi.check(lib.pperm_job_report(ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                        ctypes.c_void_p(stream.cuda_stream), ctypes.byref(rep)), "pperm_job_report")
+    return {f: getattr(rep, f) for f, _ in _abi.JobReport._fields_}
 
 
 def run_job(problems, schedules, stream=None):

@@ -114,3 +114,42 @@ def test_job_mix_subset_matches_lockstep():
     run_schedules(stepped, scheds)
     for i, (g, h) in enumerate(zip(chained, stepped)):
         _assert_same(_state(g), _state(h), f"mix problem {i}")
+
+
+def test_step_cap_stops_only_its_problem_and_is_reported():
+    # problem 1 hits its step cap in its third epoch: it stops after that
+    # epoch and reports EOVERFLOW; the others run their whole schedules, bit
+    # for bit as alone; the launch's report counts the failure and nothing else
+    from paper_2002_03000_amd import ParallelFlatPERM, PPermError, job_report, run_job
+    specs = [(2, 60, 40, 61), (2, 200, 30, 62), (3, 50, 25, 63)]
+    scheds = [[1, 1, 2, 4], [1, 1, 2, 4, 8], [1, 2, 3]]
+    caps = [0, 2000, 0]
+    gs = [ParallelFlatPERM(d, n, N, sd, stream_id=i, step_cap=caps[i]) for i, (d, n, N, sd) in enumerate(specs)]
+    ws = run_job(gs, scheds)
+    rep = job_report(ws)
+    print(f"job report: {rep}", flush=True)
+    assert rep["problems_failed"] == 1 and rep["problems_incomplete"] == 0
+    assert rep["waves_left_idle"] == 0 and rep["problems_finished"] == 3
+    with pytest.raises(PPermError, match="EOVERFLOW"):
+        gs[1].estimates()
+    st = gs[1].sequence_stats()
+    assert st["capped"].any()
+    # the capped problem ran no epoch after the one in which the cap hit: its
+    # sequences' tour counters stop there (the oracle, capped the same way,
+    # names that epoch)
+    o = oracle.Oracle(2, 200, 30, 62, stream=1, step_cap=2000)
+    ran = 0
+    for T in scheds[1]:
+        capped = o.run_tours(T)
+        o.merge_epoch()
+        ran += T
+        if capped:
+            break
+    assert ran < sum(scheds[1])
+    assert np.array_equal(gs[1].view("t").cpu().numpy().view(np.uint64), o.t)
+    for i in (0, 2):
+        alone = ParallelFlatPERM(specs[i][0], specs[i][1], specs[i][2], specs[i][3], stream_id=i)
+        for T in scheds[i]:
+            alone.run_tours(T)
+            alone.merge_epoch()
+        _assert_same(_state(gs[i]), _state(alone), f"uncapped problem {i}")

@@ -1,4 +1,4 @@
-"""Observables through the ratio estimator of eqn (42MC): <R^2_n>.
+"""Observables through the ratio estimator of eqn (5): <R^2_n>.
 
 The device keeps, beside every weight sum, the sum of W * R^2 over the same
 samples and merges it through the same pairwise tree.  Every per-sequence and
