@@ -185,6 +185,21 @@ int pperm_batch_workspace_bytes(size_t count, size_t* bytes);
 int pperm_run_batch(pperm_ctx* const* ctxs, size_t count, const uint32_t* tours_each,
                     void* d_workspace, size_t bytes, void* hip_stream);
 
+/* pperm_run_batch for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same launches, the same bits, with the launch entries and queue words
+ * in a fixed scratch array of the library (one per device, about 96 KiB, held
+ * until the process ends) instead of a caller workspace.  At most
+ * PPERM_NOALLOC_MAX_PROBLEMS contexts per call (EINVAL beyond).  The problem
+ * classes run one after another on hip_stream (NULL: the default stream) with
+ * no library streams.  Every call on a device shares that device's scratch, so
+ * calls that overlap on one device (other streams, other threads) race; calls
+ * in order on one stream do not.  Allocates no device memory.  Errors: as
+ * pperm_run_batch. */
+#define PPERM_NOALLOC_MAX_PROBLEMS 4096u
+int pperm_run_batch_noalloc(pperm_ctx* const* ctxs, size_t count, const uint32_t* tours_each,
+                            void* hip_stream);
+
 /* One epoch -- pperm_run_tours(tours) then pperm_merge_epoch -- captured once
  * as a HIP graph and replayed: each pperm_epoch_graph_launch enqueues the
  * whole epoch on the context's stream with one launch, with exactly the

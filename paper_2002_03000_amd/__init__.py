@@ -13,7 +13,7 @@ from ._abi import PPermError, load as load_library, LIB_PATH  # noqa: F401
 def __getattr__(name):
     # the binding imports torch; keep `import paper_2002_03000_amd` light
     if name in ("ParallelFlatPERM", "Batch", "run_schedules", "run_job", "run_job_sliced", "Server", "pool_script",
-                "job_report", "probe",
+                "run_batch_noalloc", "job_report", "probe",
                 "autotune",
                 "EpochGraph"):
         from . import sampler

@@ -21,6 +21,7 @@ JOB_QUEUED, JOB_ACTIVE, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
 
 ERRORS = {0: "PPERM_OK", -1: "PPERM_EINVAL", -2: "PPERM_ENOMEM", -3: "PPERM_EDEVICE",
           -4: "PPERM_ESTATE", -5: "PPERM_ERANGE", -6: "PPERM_EOVERFLOW", -7: "PPERM_EINCOMPLETE"}
+NOALLOC_MAX_PROBLEMS = 4096
 
 
 class Config(ctypes.Structure):
@@ -91,6 +92,7 @@ SIGNATURES = {
     "pperm_merge_epoch": (_int, [_vp]),
     "pperm_batch_workspace_bytes": (_int, [_sz, _c.POINTER(_sz)]),
     "pperm_run_batch": (_int, [_c.POINTER(_vp), _sz, _c.POINTER(_u32), _vp, _sz, _vp]),
+    "pperm_run_batch_noalloc": (_int, [_c.POINTER(_vp), _sz, _c.POINTER(_u32), _vp]),
     "pperm_epoch_graph_create": (_int, [_vp, _u32, _c.POINTER(_vp)]),
     "pperm_epoch_graph_launch": (_int, [_vp]),
     "pperm_epoch_graph_destroy": (_int, [_vp]),

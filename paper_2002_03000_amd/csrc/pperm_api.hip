@@ -664,6 +664,25 @@ int pperm_run_batch(pperm_ctx* const* ctxs, size_t count, const uint32_t* tours_
                        (hipStream_t)hip_stream, ds);
 }
 
+int pperm_run_batch_noalloc(pperm_ctx* const* ctxs, size_t count, const uint32_t* tours_each,
+                            void* hip_stream) {
+    if (!ctxs || !tours_each || count == 0) return PPERM_EINVAL;
+    if (count > NOALLOC_MAX_PROBLEMS) return PPERM_EINVAL;
+    int device = -1;
+    HIP_TRY(hipGetDevice(&device));
+    // the library's scratch on this device (its address, never its host name)
+    void* base = nullptr;
+    size_t cap = 0;
+    HIP_TRY(noalloc_scratch(&base, &cap));
+    if (NOALLOC_QUEUE_BYTES + count * sizeof(LaunchEntry) > cap) return PPERM_EINVAL;
+    BatchPlan plan;
+    int rc = plan_batch(ctxs, count, tours_each, device, &plan);
+    if (rc || plan.items.empty()) return rc;
+    unsigned char* ws = static_cast<unsigned char*>(base);
+    return launch_plan(plan, device, reinterpret_cast<LaunchEntry*>(ws + NOALLOC_QUEUE_BYTES),
+                       reinterpret_cast<uint32_t*>(ws), (hipStream_t)hip_stream, nullptr);
+}
+
 // ---- one epoch as a captured HIP graph -------------------------------------------
 struct pperm_graph {
     pperm_ctx* ctx;

@@ -203,6 +203,12 @@ hipError_t launch_batch(const BatchArgs& b, uint32_t workgroups, uint32_t lds_by
                         bool observables = false, bool long_walk = false);
 hipError_t batch_occupancy(uint32_t lds_bytes, int* blocks_per_cu);
 
+// The file-scope scratch of the allocation-free batched launch on the current
+// device: its device address (looked up once per device) and size.  Holds the
+// queue words (first 256 bytes) and the launch entries.
+constexpr uint32_t NOALLOC_MAX_PROBLEMS = 4096;
+constexpr size_t NOALLOC_QUEUE_BYTES = 256;
+hipError_t noalloc_scratch(void** ptr, size_t* bytes);
 hipError_t launch_merge_counts(const uint32_t* m, uint32_t N, uint64_t* MG, uint32_t* zero_m,
                                hipStream_t s);
 hipError_t launch_group_sums(const SumRec* L, const uint32_t* m, uint32_t N, uint32_t row,

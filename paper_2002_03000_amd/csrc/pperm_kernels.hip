@@ -26,6 +26,8 @@
 // (no contraction: the library is built with -ffp-contract=off), and the
 // random numbers are a pure function of (seed, sequence, tour, event).  The
 // launch shape therefore never changes a result.
+#include <mutex>
+
 #include "pperm_internal.h"
 
 namespace pperm {
@@ -1694,3 +1696,33 @@ hipError_t launch_merge_independent(SumRec* L, uint32_t* m, SumRec* G, uint64_t*
 }
 
 }  // namespace pperm
+
+// Scratch of the allocation-free batched launch (pperm_run_batch_noalloc): the
+// queue words of its launches, then one launch entry per problem.  Each device
+// the library runs on holds its own copy for the life of the process; calls on
+// one device share it.
+static __device__ __align__(256) unsigned char
+    scratch[pperm::NOALLOC_QUEUE_BYTES + pperm::NOALLOC_MAX_PROBLEMS * sizeof(pperm::LaunchEntry)];
+
+// The device address of `scratch` on the current device, looked up once per
+// device with that device current (the host-side name of the array is not a
+// device address and must never reach a kernel or a copy).
+hipError_t pperm::noalloc_scratch(void** ptr, size_t* bytes) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (addr[dev] == nullptr) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    *bytes = sizeof(scratch);
+    return hipSuccess;
+}

@@ -211,6 +211,20 @@ class Batch:
                    "pperm_run_batch")
 
 
+def run_batch_noalloc(problems, tours_each, stream=None):
+    """pperm_run_batch_noalloc: problems[i] runs tours_each[i] more tours, the
+    launch entries in the library's own scratch (no workspace is allocated)."""
+    lib = _abi.load()
+    count = len(problems)
+    device = problems[0].device
+    ctxs = (ctypes.c_void_p * count)(*[p._ctx for p in problems])
+    tours = (ctypes.c_uint32 * count)(*[int(t) for t in tours_each])
+    with torch.cuda.device(device):
+        stream = stream if stream is not None else torch.cuda.current_stream(device)
+        _abi.check(lib.pperm_run_batch_noalloc(ctxs, count, tours, ctypes.c_void_p(stream.cuda_stream)),
+                   "pperm_run_batch_noalloc")
+
+
 def probe(device=None, stream=None):
     """The measured ceilings of the device (pperm_probe): 32-bit VALU lane-ops/s,
     LDS bytes/s and L2 bytes/s, with the duration of each timed launch."""
