@@ -1,17 +1,19 @@
 #!/usr/bin/env python3
 """Benchmark: walk-steps/s of parallel flatPERM on one MI355X.
 
-One benchmark step is one whole job of the parallel square-lattice workload:
-4096 interacting flatPERM sequences (Algorithm 2), n_max = 500, a merge every
-64 tours, 38 epochs = 9,961,472 tours, followed by the read-out of log c_n.
-Every step runs a fresh job with its own seed; the workspaces are allocated
-and initialised before the timed region, so the timed region holds exactly the
-hot path: growth with a_+ scans, weight updates, prune/enrich, accumulation,
-merges and the estimate read-out.
+One benchmark step is one whole job of the default workload, the cubic-lattice
+configuration: 16384 interacting flatPERM sequences (Algorithm 2), n_max = 1000,
+a merge every 32 tours after the warm-up epochs, 8,388,608 tours in all,
+followed by the read-out of log c_n.  Every step runs a fresh job with its own
+seed; the workspaces are allocated and initialised before the timed region, so
+the timed region holds exactly the hot path: growth with a_+ scans, weight
+updates, prune/enrich, accumulation, merges and the estimate read-out.
 
 Printed: one JSON line with the metric, a roofline object for the dominant
-kernel (the growth kernel, timed with HIP events on its stream) and the CPU
-oracle timed on a bounded sample of the same workload.
+kernel (the growth kernel, timed with HIP events on its stream) with the
+VALU, LDS and L2 fractions against ceilings probed on the device, the
+critical-path bound, and the CPU oracle timed on bounded samples of the same
+workload (single core and all cores, median of three each).
 """
 import argparse
 import json
@@ -29,8 +31,25 @@ import workloads  # noqa: E402
 # of the minimal single-walk step: Philox4x32-10 block 100, occupancy scan
 # 7 per neighbour query with 2d - 1 queries, control 15, growth 15, record 6).
 ALG_OPS_PER_STEP = {2: 100 + 7 * 3 + 15 + 15 + 6, 3: 100 + 7 * 5 + 15 + 15 + 6}
-# MI355X 32-bit VALU peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one lane-op per lane per clock).
-ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+
+def lds_bytes_per_step(dim, n_max):
+    """Algorithmic LDS bytes per walk-step: 2d - 1 occupancy-key reads and one
+    insert of the packed key (4 bytes on the square lattice and, up to
+    n_max = 1023, on the cubic one; 8 bytes for longer cubic walks)."""
+    key = 4 if (dim == 2 or n_max <= 1023) else 8
+    return 2 * dim * key
+# Algorithmic L2 bytes per walk-step: the pooled sum of the length read (8),
+# the sequence's sum read and written (16) and its count read and written (8).
+L2_BYTES_PER_STEP = 32
+# MI355X 32-bit VALU peak: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz = 78.6 T lane-op/s, the
+# published FP32 vector rate (157.3 TFLOP/s) with one operation per FMA.  (FP64 operations,
+# most of the prune/enrich arithmetic, issue at half that rate.)
+ALU_PEAK_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12
+
+# the headline metric: walk-steps/s (with the relative error of c_{n_max} at
+# the run's fixed budget beside it) of plain, batched and served flatPERM
+METRIC = "walk-steps/s and c_n rel. error at fixed budget, batched/served vs plain, 1 GPU"
 
 PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2002_03000_amd", "csrc", "pperm_kernels.hip")
@@ -81,13 +100,23 @@ def describe(p):
             f"then {p.epochs - 1} x {p.tours_per_epoch} tours/sequence ({p.total_tours} tours)")
 
 
-def cpu_baseline(p, budget_s=15.0):
-    """The oracle, as it stands, on a bounded sample of the same job: its epochs
-    in order (run + merge, all sequences, all host cores) until the time budget
-    is spent, stopping at an epoch boundary."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def oracle_rate(p, threads, budget_s):
+    """The oracle, as it stands, on the job's epochs in order (run + merge,
+    every sequence) until budget_s is spent, stopping at an epoch boundary.
+    Returns (walk-steps/s, walk-steps, epochs, seconds)."""
     import oracle
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
-    o = oracle.Oracle(p.dim, p.n_max, p.n_sequences, p.seed, threads=threads)
+    o = oracle.Oracle(p.dim, p.n_max, p.n_sequences, p.seed, stream=p.stream, threads=threads)
     done, t0 = 0, time.perf_counter()
     for T in p.schedule():
         o.run_tours(T)
@@ -97,9 +126,38 @@ def cpu_baseline(p, budget_s=15.0):
             break
     dt = time.perf_counter() - t0
     steps = o.walk_steps()
-    return {"value": steps / dt, "unit": "walk-steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"the first {done} epochs of the same job ({steps} walk-steps, "
-                      f"{o.N * int(o.MG[0]) // max(o.N, 1)} tours) in {dt:.2f} s"}
+    return steps / dt, steps, done, dt
+
+
+def cpu_baseline(p, budget_s=4.0, runs=3):
+    """The oracle on bounded samples of the same job: single core and all host
+    cores, each the median of `runs` runs of about budget_s seconds."""
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
+    single = [oracle_rate(p, 1, budget_s) for _ in range(runs)]
+    allc = [oracle_rate(p, threads, budget_s) for _ in range(runs)]
+    med = lambda xs: float(sorted(x[0] for x in xs)[len(xs) // 2])
+    a = sorted(allc, key=lambda x: x[0])[len(allc) // 2]
+    return {"value": med(allc), "unit": "walk-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"the job's first epochs in order, about {budget_s:.0f} s per run, median of {runs} "
+                      f"runs (all cores: {a[2]} epochs, {a[1]} walk-steps in {a[3]:.2f} s)",
+            "single_core": {"value": med(single), "runs": [x[0] for x in single],
+                            "epochs": [x[2] for x in single]},
+            "all_cores": {"value": med(allc), "runs": [x[0] for x in allc], "epochs": [x[2] for x in allc]},
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+
+
+def probed_roofline(dim, n_max, steps_per_s, ops_per_step, probes):
+    """Achieved fractions of the probed VALU, LDS and L2 ceilings at the growth
+    kernel's walk-step rate (algorithmic work per step)."""
+    out = {}
+    for name, per_step, peak, unit in (
+            ("valu", ops_per_step, probes["valu_lane_ops_per_s"], "lane-op/s"),
+            ("lds", lds_bytes_per_step(dim, n_max), probes["lds_bytes_per_s"], "B/s"),
+            ("l2", L2_BYTES_PER_STEP, probes["l2_bytes_per_s"], "B/s")):
+        ach = steps_per_s * per_step
+        out[name] = {"achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak, "per_step": per_step}
+    out["binding_of_three"] = max(("valu", "lds", "l2"), key=lambda k: out[k]["frac"])
+    return out
 
 
 def main():
@@ -107,7 +165,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="default 3 (long2d: 1)")
     ap.add_argument("--warmup", type=int, default=None, help="default 1 (long2d: 0)")
-    ap.add_argument("--workload", default="parallel2d", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="parallel3d", choices=sorted(WORKLOADS))
     ap.add_argument("--epochs", type=int, default=0, help="override the epoch count (profiling)")
     ap.add_argument("--walks-per-wave", type=int, default=0)
     ap.add_argument("--hash-slots", type=int, default=0)
@@ -121,12 +179,19 @@ def main():
     ap.add_argument("--compare-n", default="1,2,12,64", help="compare: sequence counts")
     ap.add_argument("--compare-s", default="1,10,100,1000,10000", help="compare: tours per sequence")
     ap.add_argument("--compare-replicas", type=int, default=8, help="compare: independent runs per cell")
+    ap.add_argument("--compare-t", default="64,1", help="compare: Algorithm 2 tours per epoch")
+    ap.add_argument("--compare-nmax", type=int, default=500, help="compare: maximum walk length")
     ap.add_argument("--serve-duration", type=float, default=60.0, help="served: arrival window (s)")
     ap.add_argument("--serve-rate", type=float, default=50.0, help="served: arrivals per second")
-    ap.add_argument("--serve-cap", type=int, default=4096, help="served: tour cap per job")
+    ap.add_argument("--serve-cap", type=int, default=1_000_000, help="served: tour cap per job")
     ap.add_argument("--serve-target", type=float, default=1e-3, help="served: relative-error target")
     ap.add_argument("--serve-pool-gib", type=float, default=64.0)
     ap.add_argument("--serve-max-sequences", type=int, default=262144)
+    ap.add_argument("--plain-full", action="store_true",
+                    help="batched / served: time the plain path on every problem, not a stratified subset")
+    ap.add_argument("--plain-strata", type=int, default=32,
+                    help="batched / served: strata (by walk-steps) of the plain-path subset")
+    ap.add_argument("--no-probe", action="store_true", help="skip the VALU / LDS / L2 ceiling probes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-latency-bound", action="store_true",
                     help="skip the critical-path replay that follows the timed region")
@@ -180,7 +245,10 @@ def main():
     if args.autotune:
         # launch shape from short trial runs, before and outside the timed region
         from paper_2002_03000_amd import autotune
-        best, tuning = autotune(p.dim, p.n_max, p.n_sequences, mode=p.mode, trial=tuple(p.schedule()[:5]))
+        # timed on the first steady-state epoch, after the warm-up epochs
+        head = len(p.schedule()) - p.epochs + 1
+        best, tuning = autotune(p.dim, p.n_max, p.n_sequences, mode=p.mode,
+                                trial=tuple(p.schedule()[:head + 1]), untimed=head)
         args.walks_per_wave, args.hash_slots = best["walks_per_wave"], best["hash_slots"]
         args.sums_global = best["sums_global"]
 
@@ -240,8 +308,9 @@ def main():
     rel_err = float(np.std(np.exp(est_top - est_top.mean()), ddof=1)) if len(results) > 1 else None
 
     kernel = "batch_long_kernel" if (args.workload == "long2d" or args.sums_global) else "batch_kernel"
+    probes = None if args.no_probe else probe_ceilings()
     line = {
-        "metric": "walk-steps/s (parallel flatPERM, 1 GPU)",
+        "metric": METRIC,
         "value": value,
         "unit": "walk-steps/s",
         "n_gpus": 1,
@@ -266,14 +335,36 @@ def main():
                      "traffic": measured_traffic(f"{kernel}_{args.workload}_traffic.md")
                      if not args.epochs else None,
                      "kernel": kernel, "avg_launch_ms": run_ms / launches,
-                     "alg_ops_per_step": ops},
+                     "alg_ops_per_step": ops,
+                     "probed": probed_roofline(p.dim, p.n_max, kernel_rate, ops, probes) if probes else None},
+        "probes": probes,
         "cpu_baseline": None,
     }
+    if args.workload == "long2d":
+        line["gamma_nmin"] = gamma_extrapolation(results[0][0], p.n_max)
     if not args.no_latency_bound:
         line["latency_bound"] = latency_bound(p, make, sched, elapsed / args.steps, args.sums_global)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(p)
     print(json.dumps(line), flush=True)
+
+
+def probe_ceilings():
+    """VALU, LDS and L2 ceilings of this device, measured by the library's probes."""
+    from paper_2002_03000_amd import probe
+    return probe()
+
+
+def gamma_extrapolation(log_c, n_max):
+    """gamma from eqn-(16) fits over n >= n_min, extrapolated against n_min
+    (three parameters, and two with the literature mu of the square lattice)."""
+    from paper_2002_03000_amd import analysis
+    n_mins = [m for m in (50, 100, 200, 400, 800, 1600) if m < n_max // 4]
+    if len(n_mins) < 3:
+        return None
+    free = analysis.gamma_nmin_extrapolation(log_c, n_mins, n_max=n_max)
+    fixed = analysis.gamma_nmin_extrapolation(log_c, n_mins, n_max=n_max, log_mu=0.970081147258)
+    return {"three_parameter": free, "two_parameter_mu_fixed": fixed}
 
 
 def latency_bound(p, make, sched, seconds_per_job, sums_global=False):
@@ -337,7 +428,40 @@ def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_batched(args, plain_budget_s=40.0):
+def stratified_plain(steps_each, run_one, strata, full):
+    """The plain path's time for a whole problem set, at equal work.  Every
+    problem's walk-steps are known exactly from the batched or served run
+    (both paths give the same bits, hence the same steps).  With `full` every
+    problem is timed alone; otherwise the problems are sorted by walk-steps
+    into `strata` groups, the middle problem of each group is timed alone, and
+    its time scaled by its group's walk-steps over its own stands for the
+    group.  run_one(i) returns (seconds, walk-steps) of problem i alone."""
+    import numpy as np
+    steps_each = np.asarray(steps_each, dtype=np.int64)
+    order = np.argsort(steps_each, kind="stable")
+    groups = [[int(i)] for i in order] if full else \
+        [list(map(int, g)) for g in np.array_split(order, min(strata, len(order))) if len(g)]
+    est, timed_s, timed_steps, last = 0.0, 0.0, 0, time.perf_counter()
+    for k, grp in enumerate(groups):
+        rep = grp[len(grp) // 2]
+        dt, st = run_one(rep)
+        if st != int(steps_each[rep]):
+            raise RuntimeError(f"problem {rep}: {st} walk-steps alone, {int(steps_each[rep])} in the mix")
+        est += dt * float(steps_each[grp].sum()) / max(st, 1)
+        timed_s += dt
+        timed_steps += st
+        if time.perf_counter() - last > 10:
+            last = time.perf_counter()
+            _log(f"plain path: {k + 1}/{len(groups)} timed, {timed_s:.1f} s")
+    total = int(steps_each.sum())
+    return {"value": total / est, "unit": "walk-steps/s", "seconds_for_the_set": est,
+            "walk_steps": total, "timed_problems": len(groups), "timed_seconds": timed_s,
+            "timed_walk_steps": timed_steps,
+            "method": "every problem alone" if full else
+            f"one problem per stratum of {len(groups)} strata by walk-steps, scaled by the stratum's walk-steps"}
+
+
+def run_batched(args):
     """The 256-problem mix as one batched job: in each round every problem that
     still has an epoch runs it, all of them in one batched launch, then each
     merges.  Beside it: the same problems on the single-problem path one at a
@@ -358,8 +482,9 @@ def run_batched(args, plain_budget_s=40.0):
         return ParallelFlatPERM(p.dim, p.n_max, p.n_sequences, p.seed + offset, mode=p.mode,
                                 stream_id=p.stream)
 
-    from paper_2002_03000_amd import run_job
+    from paper_2002_03000_amd import job_report, run_job
     batch = Batch(len(mix))
+    report = None
     # warm-up: the first two epochs of a few problems, their own seeds
     warm = [make(p, 7_000_000) for p in mix[:8]]
     if args.lockstep:
@@ -410,13 +535,17 @@ def run_batched(args, plain_budget_s=40.0):
                 if time.perf_counter() - last > 10:
                     last = time.perf_counter()
                     _log(f"batched job {k}: running, {last - t0:.0f} s")
+            report = job_report(ws)
             del ws
         ests = [g.estimates() for g in probs]
         torch.cuda.synchronize()
         elapsed_total += time.perf_counter() - t0
         by_dim = {2: 0, 3: 0}
-        for p, g in zip(mix, probs):
-            by_dim[p.dim] += g.stats()["steps"]
+        per = [g.stats()["steps"] for g in probs]
+        if k == 0:
+            steps_first = per
+        for p, st in zip(mix, per):
+            by_dim[p.dim] += st
         steps_total += sum(by_dim.values())
         results.append(ests)
         for g in probs:
@@ -429,30 +558,29 @@ def run_batched(args, plain_budget_s=40.0):
     ops = (ALG_OPS_PER_STEP[2] * by_dim[2] + ALG_OPS_PER_STEP[3] * by_dim[3]) / max(1, sum(by_dim.values()))
     achieved = steps_total / (run_ms / 1e3) * ops / 1e12
 
-    # plain path, one problem at a time, same problems and seeds (offset 0)
-    t0 = time.perf_counter()
-    plain_steps, plain_problems, plain_epochs = 0, 0, 0
-    for p, sch in zip(mix, scheds):
-        g = make(p, 0)
-        for T in sch:
+    # the plain path on the same problems and seeds (those of the first timed
+    # job), one problem at a time through pperm_run_tours / pperm_merge_epoch
+    def plain_one(i):
+        g = make(mix[i], 0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for T in scheds[i]:
             g.run_tours(T)
             g.merge_epoch()
-            torch.cuda.synchronize()
-            plain_epochs += 1
-            if time.perf_counter() - t0 > plain_budget_s:
-                break
         g.estimates()
-        plain_steps += g.stats()["steps"]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = g.stats()["steps"]
         g.close()
-        plain_problems += 1
-        if time.perf_counter() - t0 > plain_budget_s:
-            break
-    plain_dt = time.perf_counter() - t0
-    _log(f"plain path: {plain_problems} problems, {plain_epochs} epochs in {plain_dt:.1f} s")
+        return dt, st
+
+    plain = stratified_plain(steps_first, plain_one, args.plain_strata, args.plain_full)
+    _log(f"plain path: {plain['timed_problems']} problems timed in {plain['timed_seconds']:.1f} s, "
+         f"{plain['value']:.3e} walk-steps/s")
 
     total_tours = sum(p.total_tours for p in mix)
     line = {
-        "metric": "walk-steps/s (parallel flatPERM, 1 GPU)",
+        "metric": METRIC,
         "value": value,
         "unit": "walk-steps/s",
         "n_gpus": 1,
@@ -470,9 +598,9 @@ def run_batched(args, plain_budget_s=40.0):
                                   "epochs chained on the device in one persistent launch per LDS class"),
                    "problems": len(mix), "rounds": rounds, "lockstep": bool(args.lockstep),
                    "walk_steps_per_job": steps_total // args.steps},
-        "plain_path": {"value": plain_steps / plain_dt, "unit": "walk-steps/s",
-                       "sample": f"the first {plain_problems} problems of the mix one at a time "
-                                 f"({plain_epochs} epochs, {plain_steps} walk-steps) in {plain_dt:.2f} s"},
+        "plain_path": plain,
+        "batched_vs_plain": value / plain["value"],
+        "job_report": report,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
                      "frac": achieved / ALU_PEAK_TOPS, "traffic": None,
                      "kernel": "batch_kernel" if args.lockstep else "job_kernel",
@@ -485,7 +613,7 @@ def run_batched(args, plain_budget_s=40.0):
     print(json.dumps(line), flush=True)
 
 
-def run_served(args, plain_budget_s=30.0):
+def run_served(args):
     """A Poisson stream of sampling jobs served with continuous batching: jobs
     arrive in real time, are admitted by workspace footprint and active
     sequences, advance their epochs at their own pace in each server step (one
@@ -514,6 +642,7 @@ def run_served(args, plain_budget_s=30.0):
     srv = Server(pool, args.serve_max_sequences)
     arrival, index = {}, {}
     lat = np.full(len(jobs), np.nan)
+    job_steps = [0] * len(jobs)
     steps_done, step_events, active_sum, n_steps = 0, [], 0, 0
     stops = {1: 0, 2: 0}
     nxt = 0
@@ -546,6 +675,7 @@ def run_served(args, plain_budget_s=30.0):
                 raise RuntimeError(f"served job {index[jid]} failed: {info}")
             lat[index[jid]] = tnow - arrival[jid]
             steps_done += info["steps"]
+            job_steps[index[jid]] = info["steps"]
             stops[info["stop"]] = stops.get(info["stop"], 0) + 1
             srv.release(jid)
         if time.perf_counter() - last > 10:
@@ -557,25 +687,44 @@ def run_served(args, plain_budget_s=30.0):
     gpu_ms = sum(a.elapsed_time(b) for a, b in step_events)
     value = steps_done / elapsed
 
-    # the plain path on the same jobs, one at a time (same results by construction)
-    t1 = time.perf_counter()
-    plain_steps, plain_jobs = 0, 0
-    for j in jobs:
-        one = Server(256 << 20, 4096)
-        jid = one.submit_problem(j.problem, j.tour_cap, j.target_rel_err)
-        while one.info(jid)["state"] not in ("done", "failed"):
-            one.step()
-        plain_steps += one.info(jid)["steps"]
-        one.close()
-        plain_jobs += 1
-        if time.perf_counter() - t1 > plain_budget_s:
-            break
-    plain_dt = time.perf_counter() - t1
+    # the plain path on the same jobs: each job alone through pperm_run_tours /
+    # pperm_merge_epoch, its stop rule checked on the host after every merge
+    # (the same rule, the same bits, hence the same walk-steps)
+    from paper_2002_03000_amd import ParallelFlatPERM
+
+    def plain_one(i):
+        j = jobs[i]
+        p = j.problem
+        g = ParallelFlatPERM(p.dim, p.n_max, p.n_sequences, p.seed, mode=p.mode, stream_id=p.stream,
+                             group_stats=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        M = 0
+        for T in workloads.Problem(p.dim, p.n_max, p.n_sequences, p.tours_per_epoch, 1 << 30, p.seed,
+                                   stream=p.stream).schedule():
+            g.run_tours(T)
+            g.merge_epoch()
+            M += p.n_sequences * T
+            rel, _ = g.error_estimate()
+            if (j.target_rel_err > 0 and rel <= j.target_rel_err) or M >= j.tour_cap:
+                break
+        g.estimates()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = g.stats()["steps"]
+        g.close()
+        return dt, st
+
+    done_idx = [i for i in range(len(jobs)) if job_steps[i] > 0]
+    plain = stratified_plain([job_steps[i] for i in done_idx], lambda k: plain_one(done_idx[k]),
+                             min(args.plain_strata, 16), args.plain_full)
+    _log(f"plain path: {plain['timed_problems']} jobs timed in {plain['timed_seconds']:.1f} s, "
+         f"{plain['value']:.3e} walk-steps/s")
 
     ops = (ALG_OPS_PER_STEP[2] + ALG_OPS_PER_STEP[3]) / 2
     achieved = steps_done / (gpu_ms / 1e3) * ops / 1e12
     line = {
-        "metric": "walk-steps/s (parallel flatPERM, 1 GPU)",
+        "metric": METRIC,
         "value": value,
         "unit": "walk-steps/s",
         "n_gpus": 1,
@@ -597,9 +746,9 @@ def run_served(args, plain_budget_s=30.0):
         "server": {"steps": n_steps, "mean_active_jobs": active_sum / max(1, n_steps),
                    "stopped_by_target": stops.get(1, 0), "stopped_by_cap": stops.get(2, 0),
                    "gpu_busy_frac": gpu_ms / 1e3 / elapsed},
-        "plain_path": {"value": plain_steps / plain_dt, "unit": "walk-steps/s",
-                       "sample": f"the first {plain_jobs} jobs one at a time ({plain_steps} walk-steps) "
-                                 f"in {plain_dt:.2f} s"},
+        "plain_path": plain,
+        "served_vs_plain": value / plain["value"],
+        "offered_walk_steps_per_s": steps_done / args.serve_duration,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
                      "frac": achieved / ALU_PEAK_TOPS, "traffic": None,
                      "kernel": "server step (job_kernel, time-sliced)", "avg_launch_ms": gpu_ms / max(1, n_steps),
@@ -627,46 +776,64 @@ def tour_schedule(S, T=64):
 def run_compare(args):
     """Algorithm 1 (independent sequences, estimates combined by the arithmetic
     mean of eqn (7) and by the geometric mean) against Algorithm 2 (shared
-    running averages) on the square lattice at n_max = 500: T_M of eqn (9)
-    against a reference run 15x longer than the longest compared run, and the
-    band width E of the eqn-(15) fit, for N sequences and S tours per
-    sequence (the layout of the paper's Tables 3 and 4)."""
+    running averages, merged every T tours for each T of --compare-t; T = 1 is
+    closest to the paper's continuous sharing) on the square lattice: T_M of
+    eqn (9) against a longer reference run of Algorithm 2, the band width E of
+    the eqn-(16) fit, and log c_{n_max}, for N sequences and S tours per
+    sequence (the layout of the paper's Tables 1-4 at --compare-nmax 10000).
+    Every cell is --compare-replicas independent problems; all of them run
+    together as lock-step batched rounds (each problem's epochs exactly as
+    alone, long walks in classes of their own)."""
     import numpy as np
     import torch
     from paper_2002_03000_amd import ParallelFlatPERM, analysis, run_schedules
 
     torch.cuda.set_device(0)
-    n_max = 500
-    ref_p = workloads.PARALLEL_2D
+    n_max = args.compare_nmax
+    # the reference: Algorithm 2 with many sequences, many more tours than any
+    # compared run (the square-lattice job at n_max <= 500, the long-walk job
+    # at longer lengths)
+    ref_p = workloads.PARALLEL_2D if n_max <= 500 else workloads.LONG_2D
     ref = ParallelFlatPERM(2, n_max, ref_p.n_sequences, 900_001, mode="shared")
+    t0 = time.perf_counter()
     for T in ref_p.schedule():
         ref.run_tours(T)
         ref.merge_epoch()
     log_best, _, ref_tours = ref.estimates()
     ref.close()
     ref_fit = analysis.ratio_fit(log_best)
-    _log(f"reference: {ref_tours} tours, mu {ref_fit['mu']:.6f}, gamma {ref_fit['gamma']:.4f}")
+    _log(f"reference: {ref_tours} tours in {time.perf_counter() - t0:.0f} s, mu {ref_fit['mu']:.6f}, "
+         f"gamma {ref_fit['gamma']:.4f}, log c_n_max {log_best[n_max]:.3f}")
 
     Ns = [int(x) for x in args.compare_n.split(",")]
     Ss = [int(x) for x in args.compare_s.split(",")]
+    Ts = [int(x) for x in args.compare_t.split(",")]
     R = args.compare_replicas
-    # every (algorithm, N, S, replica) is one problem; all of them run together
-    # as lock-step batched rounds (each problem's epochs exactly as alone)
     cells, probs, scheds = [], [], []
     seed = 910_000
     for N in Ns:
         for S in Ss:
-            for mode in ("independent", "shared"):
-                if mode == "shared" and N == 1:
-                    continue                      # one sequence: the two algorithms coincide
+            kinds = [("independent", 64)] + [("shared", T) for T in Ts]
+            for mode, T in kinds:
+                if mode == "shared" and N == 1 and T != Ts[0]:
+                    continue                      # one sequence: T changes nothing
                 for r in range(R):
                     seed += 1
-                    cells.append((mode, N, S, r))
+                    cells.append((mode, T, N, S, r))
                     probs.append(ParallelFlatPERM(2, n_max, N, seed, mode=mode, stream_id=len(probs)))
-                    scheds.append(tour_schedule(S))
+                    scheds.append(tour_schedule(S, T))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    run_schedules(probs, scheds)
+    # Algorithm 2 problems whose sums fit in LDS chain their epochs on the
+    # device (pperm_run_job: one launch, however many epochs); the others run
+    # as lock-step batched rounds
+    from paper_2002_03000_amd import run_job
+    chain = [i for i, (mode, T, N, S, r) in enumerate(cells) if mode == "shared" and n_max <= 2048]
+    rest = [i for i in range(len(cells)) if i not in set(chain)]
+    if chain:
+        job_ws = run_job([probs[i] for i in chain], [scheds[i] for i in chain])
+    if rest:
+        run_schedules([probs[i] for i in rest], [scheds[i] for i in rest])
     done = torch.cuda.Event()
     done.record()
     last = t0
@@ -677,44 +844,51 @@ def run_compare(args):
             _log(f"compare: {len(probs)} problems running, {last - t0:.0f} s")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    steps = {"independent": 0, "shared": 0}
+    if chain:
+        del job_ws
+    steps = {}
     results = {}
-    for (mode, N, S, r), g in zip(cells, probs):
-        steps[mode] += g.stats()["steps"]
+    for (mode, T, N, S, r), g in zip(cells, probs):
         lc, _, _ = g.estimates()
         if mode == "independent":
             per = g.sequence_log_estimates()
             ests = {"alg1_mean": lc, "alg1_geometric": analysis.combine_geometric(per)}
+            steps["alg1"] = steps.get("alg1", 0) + g.stats()["steps"]
         else:
-            ests = {"alg2": lc}
+            ests = {f"alg2_T{T}": lc}
+            steps[f"alg2_T{T}"] = steps.get(f"alg2_T{T}", 0) + g.stats()["steps"]
         for kind, est in ests.items():
             fin = np.isfinite(est)
             top = int(np.max(np.nonzero(fin)[0])) if fin.any() else 0
             tm = analysis.total_abs_error(log_best, est, M=top) if top > 0 else float("nan")
             e = analysis.ratio_fit(est, n_max=top)["E"] if top > 3 else float("nan")
-            results.setdefault((kind, N, S), []).append((tm, e, top))
+            results.setdefault((kind, N, S), []).append((tm, e, top, est[n_max]))
         g.close()
-    table = {"T_M": {}, "T_M_se": {}, "E": {}, "E_se": {}, "sampled_lengths_min": {}}
+    table = {"T_M": {}, "T_M_se": {}, "E": {}, "E_se": {}, "log_c_nmax": {}, "log_c_nmax_se": {},
+             "sampled_lengths_min": {}}
     for (kind, N, S), vals in sorted(results.items()):
         v = np.array(vals, dtype=np.float64)
-        for name, col in (("T_M", 0), ("E", 1)):
+        for name, col in (("T_M", 0), ("E", 1), ("log_c_nmax", 3)):
             x = v[:, col]
-            table[name].setdefault(kind, {}).setdefault(f"N={N}", {})[f"S={S}"] = float(np.nanmean(x))
+            ok = np.isfinite(x)
+            table[name].setdefault(kind, {}).setdefault(f"N={N}", {})[f"S={S}"] = \
+                float(np.mean(x[ok])) if ok.any() else None
             table[name + "_se"].setdefault(kind, {}).setdefault(f"N={N}", {})[f"S={S}"] = \
-                float(np.nanstd(x, ddof=1) / np.sqrt(np.sum(np.isfinite(x)))) if len(x) > 1 else None
+                float(np.std(x[ok], ddof=1) / np.sqrt(ok.sum())) if ok.sum() > 1 else None
         table["sampled_lengths_min"].setdefault(kind, {}).setdefault(f"N={N}", {})[f"S={S}"] = int(v[:, 2].min())
     line = {
-        "metric": "T_M (eqn 9) and band width E (eqn 15 fit): Algorithm 1 vs Algorithm 2, 1 GPU",
+        "metric": "T_M (eqn 9), band width E (eqn 16 fit) and log c_n_max: Algorithm 1 vs Algorithm 2, 1 GPU",
         "unit": "log units",
         "n_gpus": 1,
         "data": "synthetic (walks grown from parameters)",
         "config": {"workload": f"square lattice, n_max={n_max}, N in {Ns}, S tours per sequence in {Ss}, "
-                               f"{R} replicas per cell (all cells in one set of batched rounds); "
-                               f"reference: Algorithm 2, N=4096, {ref_tours} tours",
-                   "reference_fit": ref_fit, "replicas": R},
+                               f"Algorithm 2 merged every T in {Ts} tours (after warm-up epochs 1, 1, 2, ... "
+                               f"up to T), {R} replicas per cell; reference: Algorithm 2, "
+                               f"N={ref_p.n_sequences}, {ref_tours} tours",
+                   "reference_fit": ref_fit, "reference_log_c_nmax": float(log_best[n_max]), "replicas": R},
         "tables": table,
-        "walk_steps": {"alg1": steps["independent"], "alg2": steps["shared"]},
-        "walk_steps_per_s_all": (steps["independent"] + steps["shared"]) / elapsed,
+        "walk_steps": steps,
+        "walk_steps_per_s_all": sum(steps.values()) / elapsed,
         "seconds": elapsed,
     }
     print(json.dumps(line), flush=True)

@@ -179,9 +179,10 @@ int pperm_batch_workspace_bytes(size_t count, size_t* bytes);
  * be ordered after all earlier work of the contexts (simplest: create every
  * context on `hip_stream`).  d_workspace: caller-owned device memory of at least
  * pperm_batch_workspace_bytes(count), 256-byte aligned, not in use by another
- * batch in flight.  Not thread-safe per device.  Errors: EINVAL (bad arguments,
- * a context twice, contexts on another device, a context with observables or
- * with its per-length sums in global memory), EOVERFLOW, EDEVICE. */
+ * batch in flight.  Contexts whose per-length sums stay in global memory (long
+ * walks, PPERM_FLAG_SUMS_GLOBAL) run in classes of their own.  Not thread-safe
+ * per device.  Errors: EINVAL (bad arguments, a context twice, contexts on
+ * another device, a context with observables), EOVERFLOW, EDEVICE. */
 int pperm_run_batch(pperm_ctx* const* ctxs, size_t count, const uint32_t* tours_each,
                     void* d_workspace, size_t bytes, void* hip_stream);
 

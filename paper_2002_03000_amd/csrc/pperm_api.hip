@@ -69,7 +69,15 @@ uint32_t log2u(uint32_t x) {
     return r;
 }
 
-uint32_t key_bytes(uint32_t dim) { return dim == 2 ? 4u : 8u; }
+// Cubic walks of at most COMPACT3_MAX_N steps run with 32-bit occupancy keys
+// in the wave-per-walk kernels (not with observables, which read coordinates
+// back from the keys); every other cubic walk with 64-bit keys.
+bool compact_key(const pperm_config* c, uint32_t walks_per_wave) {
+    return c->dim == 3 && c->n_max <= COMPACT3_MAX_N && walks_per_wave == 1 &&
+           !(c->flags & PPERM_FLAG_OBSERVABLES);
+}
+
+uint32_t key_bytes(uint32_t dim, bool compact) { return (dim == 2 || compact) ? 4u : 8u; }
 
 // Resolved tuning choices for a configuration (the "auto" values included).
 struct Shape {
@@ -79,6 +87,7 @@ struct Shape {
     uint32_t lds_wg_bytes;     // LDS of one workgroup
     uint32_t walks_per_wave;
     bool long_walk;            // per-length sums outside LDS
+    bool ckey;                 // cubic walks with 32-bit keys
 };
 
 // The occupancy table holds at most n_max + 1 sites; at least twice that many
@@ -93,12 +102,13 @@ int resolve_shape(const pperm_config* c, Shape* sh) {
     const uint64_t n1 = c->n_max + 1u;
     const uint32_t row_bytes = (uint32_t)align_up(n1, 16) * 16u;
     const bool obs = (c->flags & PPERM_FLAG_OBSERVABLES) != 0;
-    auto team_bytes = [&](uint64_t slots) {
-        return (uint32_t)align_up(slots * key_bytes(c->dim) + 2ull * n1, 16);
-    };
     uint32_t wpw = c->walks_per_wave;
     if (wpw == 0) wpw = 1u;   // default shape: one walk per wavefront
     if (!is_pow2(wpw) || wpw > (c->dim == 2 ? 16u : 8u)) return PPERM_EINVAL;
+    const bool ck = compact_key(c, wpw);
+    auto team_bytes = [&](uint64_t slots) {
+        return (uint32_t)align_up(slots * key_bytes(c->dim, ck) + 2ull * n1, 16);
+    };
     const bool force_global = (c->flags & PPERM_FLAG_SUMS_GLOBAL) != 0;
     if ((obs || force_global) && wpw != 1) return PPERM_EINVAL;
     uint64_t slots = c->hash_slots;
@@ -131,6 +141,7 @@ int resolve_shape(const pperm_config* c, Shape* sh) {
     sh->team_lanes = 64u / wpw;
     sh->lds_wg_bytes = (uint32_t)bytes;
     sh->long_walk = lng;
+    sh->ckey = ck;
     return PPERM_OK;
 }
 
@@ -325,6 +336,7 @@ int pperm_create(const pperm_config* cfg, void* d_workspace, size_t bytes, void*
     d.key0 = (uint32_t)cfg->seed;
     d.key1 = (uint32_t)(cfg->seed >> 32) ^ cfg->stream_id;
     d.step_cap = cfg->step_cap;
+    d.ckey = sh.ckey ? 1u : 0u;
     d.LR = (cfg->flags & PPERM_FLAG_OBSERVABLES) ? at<SumRec>(x, L.obs_L) : nullptr;
     x->desc_dev = reinterpret_cast<ProblemDesc*>(at<uint32_t>(x, L.ctrl) + CTRL_WORDS);
 
@@ -505,6 +517,7 @@ struct BatchItem {
     uint32_t tours;
     uint32_t lds;
     double work;
+    bool lng;        // per-length sums in global memory (the long-walk kernel)
 };
 
 }  // namespace
@@ -519,7 +532,7 @@ namespace {
 
 // A batched epoch step, planned on the host: the validated items, their LDS
 // classes (one persistent launch each) and the launch entries in class order.
-struct BatchClass { size_t begin, end; uint32_t lds; uint32_t total; };
+struct BatchClass { size_t begin, end; uint32_t lds; uint32_t total; bool lng; };
 struct BatchPlan {
     std::vector<BatchItem> items;
     std::vector<BatchClass> classes;
@@ -535,7 +548,7 @@ int plan_batch(pperm_ctx* const* ctxs, size_t count, const uint32_t* tours_each,
     for (size_t i = 0; i < count; ++i) {
         pperm_ctx* x = ctxs[i];
         if (!x || x->device != device) return PPERM_EINVAL;
-        if ((x->cfg.flags & PPERM_FLAG_OBSERVABLES) || x->long_walk) return PPERM_EINVAL;
+        if (x->cfg.flags & PPERM_FLAG_OBSERVABLES) return PPERM_EINVAL;
         for (size_t j = 0; j < i; ++j)
             if (ctxs[j] == x) return PPERM_EINVAL;          // a problem at most once per batch
         if (tours_each[i] == 0) continue;
@@ -544,18 +557,22 @@ int plan_batch(pperm_ctx* const* ctxs, size_t count, const uint32_t* tours_each,
         const uint64_t pooled = (x->cfg.mode == PPERM_SHARED) ? x->merged_tours + N * per_seq_total
                                                               : x->merged_tours + per_seq_total;
         if (pooled > 0xFFFFFFFFull || per_seq_total > 0xFFFFFFFFull) return PPERM_EOVERFLOW;
-        const uint32_t lds = x->desc.lds_team_bytes + x->desc.row * (uint32_t)sizeof(SumRec) +
+        // LDS of one walk: occupancy table and slot ids, the sequence's sums
+        // (unless they stay in global memory), the bottom of the copy stack
+        const uint32_t lds = x->desc.lds_team_bytes + (x->long_walk ? 0u : x->desc.row * (uint32_t)sizeof(SumRec)) +
                              LDS_STACK * (uint32_t)sizeof(StackEntry);
         items.push_back({x, tours_each[i], lds,
-                         (double)N * tours_each[i] * (double)(x->cfg.n_max + 1)});
+                         (double)N * tours_each[i] * (double)(x->cfg.n_max + 1), x->long_walk});
     }
     plan->classes.clear();
     plan->entries.clear();
     if (items.empty()) return PPERM_OK;
 
-    // LDS size classes (a launch gives every wave the largest share of its class);
+    // classes by kernel (sums in LDS, or in global memory for long walks) and
+    // LDS size (a launch gives every wave the largest share of its class);
     // inside a class the largest expected work goes first
     std::sort(items.begin(), items.end(), [](const BatchItem& a, const BatchItem& b) {
+        if (a.lng != b.lng) return !a.lng;
         if (a.lds != b.lds) return a.lds < b.lds;
         return a.work > b.work;
     });
@@ -564,14 +581,18 @@ int plan_batch(pperm_ctx* const* ctxs, size_t count, const uint32_t* tours_each,
         uint32_t cls = 8192;
         while (cls < items[i].lds) cls <<= 1;
         size_t j = i;
-        while (j < items.size() && items[j].lds <= cls) ++j;
-        classes.push_back({i, j, 0, 0});
+        while (j < items.size() && items[j].lng == items[i].lng && items[j].lds <= cls) ++j;
+        classes.push_back({i, j, 0, 0, items[i].lng});
         i = j;
     }
-    // fold the smallest classes together (their waves then take the larger share)
+    // fold the smallest classes of one kernel together (their waves then take
+    // the larger share) until at most kBatchStreams remain
     while (classes.size() > (size_t)kBatchStreams) {
-        classes[1].begin = classes[0].begin;
-        classes.erase(classes.begin());
+        size_t k = 0;
+        while (k + 1 < classes.size() && classes[k].lng != classes[k + 1].lng) ++k;
+        if (k + 1 == classes.size()) return PPERM_EINVAL;   // (two kernels leave at most two classes)
+        classes[k + 1].begin = classes[k].begin;
+        classes.erase(classes.begin() + (long)k);
     }
     std::vector<LaunchEntry>& host = plan->entries;
     host.resize(items.size());
@@ -616,7 +637,7 @@ int launch_plan(const BatchPlan& plan, int device, LaunchEntry* dev_entries, uin
     for (size_t c = 0; c < classes.size(); ++c) {
         const BatchClass& C = classes[c];
         int per_cu = 0;
-        HIP_TRY(batch_occupancy(C.lds, &per_cu));
+        HIP_TRY(batch_occupancy(C.lds, &per_cu, C.lng));
         if (per_cu < 1) return PPERM_EINVAL;
         uint64_t wgs = (uint64_t)per_cu * cus;
         if (wgs > C.total) wgs = C.total;
@@ -632,7 +653,7 @@ int launch_plan(const BatchPlan& plan, int device, LaunchEntry* dev_entries, uin
             HIP_TRY(hipStreamWaitEvent(ds->s[c], ds->fork, 0));
             s = ds->s[c];
         }
-        HIP_TRY(launch_batch(b, (uint32_t)wgs, C.lds, s));
+        HIP_TRY(launch_batch(b, (uint32_t)wgs, C.lds, s, false, C.lng));
         if (ds) HIP_TRY(hipEventRecord(ds->join[c], ds->s[c]));
     }
     if (ds)

@@ -22,6 +22,10 @@ enum : uint32_t { CTRL_QUEUE = 0, CTRL_ERR = 1, CTRL_WORDS = 16 };
 // Modes (same values as the ABI).
 enum : uint32_t { MODE_SHARED = 0, MODE_INDEPENDENT = 1, MODE_ROSENBLUTH = 2 };
 
+// Longest cubic walk whose sites are keyed in 32 bits (10 bits per coordinate
+// modulo 1024, see Lat3c): n_max + 1 < 1024.
+constexpr uint32_t COMPACT3_MAX_N = 1022;
+
 constexpr int STATS_WORDS = 10;
 constexpr uint32_t GROUPS = 16;
 // Copy-stack entries kept in LDS per wave-per-walk sequence (positions
@@ -91,6 +95,8 @@ struct ProblemDesc {
     uint32_t key0, key1;
     uint32_t step_cap;    // the configuration's step cap per sequence and call (0: default)
     SumRec* LR;           // [N][row] per-sequence sums of W * R^2, or nullptr
+    uint32_t ckey;        // 1: cubic walks with 32-bit keys (n_max <= COMPACT3_MAX_N)
+    uint32_t pad2;
 };
 
 // One problem's share of a launch: its tours, its step cap, and the index of
@@ -201,7 +207,7 @@ bool config_long_walk(const pperm_config* c);
 
 hipError_t launch_batch(const BatchArgs& b, uint32_t workgroups, uint32_t lds_bytes, hipStream_t s,
                         bool observables = false, bool long_walk = false);
-hipError_t batch_occupancy(uint32_t lds_bytes, int* blocks_per_cu);
+hipError_t batch_occupancy(uint32_t lds_bytes, int* blocks_per_cu, bool long_walk = false);
 
 // The file-scope scratch of the allocation-free batched launch on the current
 // device: its device address (looked up once per device) and size.  Holds the

@@ -150,7 +150,17 @@ __device__ __forceinline__ XF xf_of(const SumRec& r) { return XF{r.m, r.e}; }
 template <int D> struct Lat;
 template <> struct Lat<2> {
     using Key = uint32_t;
+    static constexpr int D = 2;
     static constexpr int DP = 4;  // direction lanes per probe window
+    __device__ static Key origin() { return pack(0, 0, 0); }
+    // neighbour key = end key + delta(dir): no field ever carries, every
+    // coordinate stays within +-n_max < 2^15 of its 2^15 offset
+    __device__ static Key delta(int dir) {
+        if (dir >= 4) return 0u;
+        const Key mag = (Key)1 << (16 * (dir >> 1));
+        return (dir & 1) ? (Key)((Key)0 - mag) : mag;
+    }
+    __device__ static Key next(Key k, Key d) { return k + d; }
     __device__ static Key pack(int x, int y, int) {
         return (uint32_t)(x + 32768) | ((uint32_t)(y + 32768) << 16);
     }
@@ -163,7 +173,15 @@ template <> struct Lat<2> {
 };
 template <> struct Lat<3> {
     using Key = uint64_t;
+    static constexpr int D = 3;
     static constexpr int DP = 8;
+    __device__ static Key origin() { return pack(0, 0, 0); }
+    __device__ static Key delta(int dir) {
+        if (dir >= 6) return 0u;
+        const Key mag = (Key)1 << (16 * (dir >> 1));
+        return (dir & 1) ? (Key)((Key)0 - mag) : mag;
+    }
+    __device__ static Key next(Key k, Key d) { return k + d; }
     __device__ static Key pack(int x, int y, int z) {
         return (uint64_t)(uint32_t)(x + 32768) | ((uint64_t)(uint32_t)(y + 32768) << 16) |
                ((uint64_t)(uint32_t)(z + 32768) << 32);
@@ -177,6 +195,34 @@ template <> struct Lat<3> {
         return (uint32_t)k * 0x9E3779B1u + (uint32_t)(k >> 32) * 0x85EBCA77u;
     }
 };
+
+// The cubic lattice for walks of at most COMPACT3_MAX_N steps, with 32-bit
+// keys: each coordinate modulo 1024 in a 10-bit field (x in bits 0-9, y in
+// 11-20, z in 22-31) with a zero guard bit between fields, the origin at 512
+// in every field.  Any two sites of one walk, and a site of the walk and a
+// neighbour of its end, differ by at most n_max + 1 <= 1023 in every
+// coordinate, so their keys differ; key 0 would need |x| + |y| + |z| >= 1536.
+// A neighbour's key is the end's key plus a per-direction offset (-1 is +1023
+// in the field), with the carry out of a field dropped at its guard bit.
+struct Lat3c {
+    static constexpr int D = 3;
+    using Key = uint32_t;
+    static constexpr uint32_t GUARD = (1u << 10) | (1u << 21);
+    __device__ static Key origin() { return 512u | (512u << 11) | (512u << 22); }
+    // offset of direction dir (+x, -x, +y, -y, +z, -z); 0 past the six
+    __device__ static Key delta(int dir) {
+        if (dir >= 6) return 0u;
+        const uint32_t sh = 11u * (uint32_t)(dir >> 1);
+        return (dir & 1) ? (1023u << sh) : (1u << sh);
+    }
+    __device__ static Key next(Key k, Key d) { return (k + d) & ~GUARD; }
+    __device__ static uint32_t hash(Key k) { return k * 0x9E3779B1u; }
+};
+
+// The lattice (key format) a walker instance uses: packed int16 coordinates,
+// or the compact cubic keys above.
+template <int D, bool CK> struct LatOf { using T = Lat<D>; };
+template <> struct LatOf<3, true> { using T = Lat3c; };
 
 __device__ __forceinline__ int dir_dx(int d) { return (d == 0) - (d == 1); }
 __device__ __forceinline__ int dir_dy(int d) { return (d == 2) - (d == 3); }
@@ -678,11 +724,12 @@ __device__ __forceinline__ uint64_t fields_lanes(uint64_t hb) {
 // written in place) and LDS holds the table, the slot ids and the stack bottom.
 constexpr uint32_t WALK_ABORTED = 0x80000000u;
 
-template <int D, bool OBS = false, bool LONG = false>
+template <int D, bool OBS = false, bool LONG = false, bool CK = false>
 __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t tours, uint32_t cap,
                                                   uint32_t s, unsigned char* lds, const SumRec* Gsrc,
                                                   bool fresh) {
-    using L_ = Lat<D>;
+    static_assert(!(OBS && CK), "observables need coordinates, which compact keys do not keep");
+    using L_ = typename LatOf<D, CK>::T;
     using Key = typename L_::Key;
     using F = Fields<D>;
     constexpr int W = F::W;                    // probe positions per direction per window
@@ -719,12 +766,10 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
     const int pdir = lane / W;
     const int poff = lane % W;
     // The walk's end is carried as its packed key; a neighbour's key is the
-    // end's key plus a per-direction offset (no field ever carries: every
-    // coordinate stays within +-n_max < 2^15 of the origin's 2^15 offset).
-    // (direction 2i steps +1 along axis i, direction 2i+1 steps -1; lanes past
-    // the 2d directions get 0 and are never selected)
-    const Key pmag = (pdir < 2 * D) ? ((Key)1 << (16 * (pdir >> 1))) : (Key)0;
-    const Key pdelta = (pdir & 1) ? (Key)((Key)0 - pmag) : pmag;
+    // end's key moved by a per-direction offset (L_::next).  Direction 2i
+    // steps +1 along axis i, direction 2i+1 steps -1; lanes past the 2d
+    // directions get offset 0 (the end itself) and are never selected.
+    const Key pdelta = L_::delta(pdir);
     // A zero the compiler cannot see through.  Indexing the per-length records
     // with it keeps the weight arithmetic in vector registers (the walk's
     // control state stays scalar) and lets the record read overlap the step
@@ -742,7 +787,7 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
     // the empty table with the origin in it, slot id of site 0
     for (uint32_t i = (uint32_t)lane; i < S; i += 64) table[i] = (Key)0;
     wave_fence();
-    const Key origin_key = L_::pack(0, 0, 0);
+    const Key origin_key = L_::origin();
     const uint32_t origin_slot = L_::hash(origin_key) >> hshift;
     if (lane == 0) {
         table[origin_slot] = origin_key;
@@ -846,7 +891,7 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
             // In a linear-probing run the key, if present, lies before the first
             // empty slot, so a direction is occupied iff a window shows the key
             // and free iff it shows an empty slot and no key.
-            const Key nk = ekey + pdelta;
+            const Key nk = L_::next(ekey, pdelta);
             const uint32_t home = L_::hash(nk) >> hshift;
             uint32_t slot = (home + (uint32_t)poff) & smask;
             Key v = table[slot];
@@ -1092,6 +1137,7 @@ __device__ __forceinline__ void batch_body(const BatchArgs& B) {
         const ProblemDesc P = load_const(E.desc);
         const uint32_t s = item - E.first_item;
         if (P.dim == 2) walk_sequence<2, OBS, LONG>(P, E.tours, E.step_cap, s, lds, P.G, false);
+        else if (!OBS && P.ckey) walk_sequence<3, false, LONG, true>(P, E.tours, E.step_cap, s, lds, P.G, false);
         else walk_sequence<3, OBS, LONG>(P, E.tours, E.step_cap, s, lds, P.G, false);
     }
 }
@@ -1382,6 +1428,7 @@ __global__ void __launch_bounds__(64) job_kernel(JobArgs A) {
         const uint32_t cap = cap64 > (1ull << 31) ? (1u << 31) : (uint32_t)cap64;
         const SumRec* Gsrc = (e == 0u) ? P.G : J.gver + (size_t)(e - 1u) * (P.row + JOB_GAP);
         const uint32_t rv = (P.dim == 2) ? walk_sequence<2>(P, tours, cap, s, lds, Gsrc, true)
+                            : P.ckey     ? walk_sequence<3, false, false, true>(P, tours, cap, s, lds, Gsrc, true)
                                          : walk_sequence<3>(P, tours, cap, s, lds, Gsrc, true);
         if ((rv & WALK_ABORTED) && lane == 0)
             __hip_atomic_fetch_or(&A.state[pi].failed, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1642,7 +1689,8 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t batch_occupancy(uint32_t lds_bytes, int* blocks_per_cu) {
+hipError_t batch_occupancy(uint32_t lds_bytes, int* blocks_per_cu, bool long_walk) {
+    if (long_walk) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_long_kernel, 64, lds_bytes);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_kernel, 64, lds_bytes);
 }
 

@@ -441,14 +441,16 @@ def pool_script(pool_bytes, ops):
 
 
 def autotune(dim, n_max, n_sequences, mode="shared", trial=(1, 1, 2, 4, 8), seed=0x5EED,
-             walks_per_wave=(1, 2, 4, 8), slot_factors=(1, 2), device=None):
+             walks_per_wave=(1, 2, 4, 8), slot_factors=(1, 2), device=None, untimed=0):
     """Choose the launch shape (walks per wave, hash slots, and for one walk
     per wave whether the per-length sums stay in global memory) for a
     configuration by timing a short trial schedule of every candidate on a
-    scratch problem with its own seed.  Launch shapes never change a result,
-    so the choice is free.  Returns (best, table): best = {"walks_per_wave",
-    "hash_slots", "sums_global", "ms"}, table = one such dict per candidate
-    that fits the device."""
+    scratch problem with its own seed: the first `untimed` epochs of `trial`
+    run untimed (warm-up epochs, whose work differs from the steady state's),
+    the rest are timed.  Launch shapes never change a result, so the choice is
+    free.  Returns (best, table): best = {"walks_per_wave", "hash_slots",
+    "sums_global", "ms"}, table = one such dict per candidate that fits the
+    device."""
     device = torch.device(device if device is not None else "cuda")
     s0 = 64
     while s0 < 2 * (n_max + 1):
@@ -473,9 +475,12 @@ def autotune(dim, n_max, n_sequences, mode="shared", trial=(1, 1, 2, 4, 8), seed
             g.close()
             g = make()
             warmed = True
+        for T in trial[:untimed]:
+            g.run_tours(T)
+            g.merge_epoch()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record(g.stream)
-        for T in trial:
+        for T in trial[untimed:]:
             g.run_tours(T)
             g.merge_epoch()
         b.record(g.stream)

@@ -97,3 +97,36 @@ def test_batched_mix_first_epochs_subset():
             g.merge_epoch()
             a.merge_epoch()
         print(f"mix epoch {e} identical", flush=True)
+
+
+def test_long_walk_contexts_batch_beside_in_lds_ones():
+    # contexts whose sums stay in global memory (a long walk, and shorter walks
+    # with the launch option) run in classes of their own, next to in-LDS
+    # contexts: each bit-identical to itself alone and to the oracle.  (The
+    # long walk runs only its first two one-tour epochs: its third would start
+    # a cascade of enrichment at lengths no sequence has reached, 1e7-8e7
+    # steps, past the default step cap of a call.)
+    from paper_2002_03000_amd import Batch, ParallelFlatPERM
+    specs = [(2, 6000, 6, 71, True), (3, 400, 24, 72, True), (2, 300, 40, 73, False),
+             (3, 900, 20, 74, False), (2, 120, 33, 75, True)]
+    mk = lambda: [ParallelFlatPERM(d, n, N, sd, stream_id=i, sums_global=sg)
+                  for i, (d, n, N, sd, sg) in enumerate(specs)]
+    batched, alone = mk(), mk()
+    os_ = [oracle.Oracle(d, n, N, sd, stream=i) for i, (d, n, N, sd, sg) in enumerate(specs)]
+    b = Batch(len(specs))
+    for e, tours in enumerate(([1] * 5, [1, 2, 1, 2, 3], [0, 1, 3, 1, 2])):
+        b.run_tours(batched, tours)
+        for a, o, t in zip(alone, os_, tours):
+            if t:
+                a.run_tours(t)
+                assert not o.run_tours(t)
+        for i, (g, a, o) in enumerate(zip(batched, alone, os_)):
+            if not tours[i]:
+                continue
+            assert _equal(_state(g), _state(a)), f"problem {i} epoch {e}: batch != alone"
+            assert_epoch_equal(g, o, label=f"long batch problem {i} epoch {e}")
+            g.merge_epoch()
+            a.merge_epoch()
+            o.merge_epoch()
+            assert_pooled_equal(g, o, f"long batch problem {i} merge {e}")
+        print(f"long-walk batch epoch {e} identical", flush=True)

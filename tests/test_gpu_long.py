@@ -64,17 +64,20 @@ def test_long_walk_observables_match_oracle():
     assert np.array_equal(a[~nan].view(np.uint64), b[~nan].view(np.uint64))
 
 
-def test_long_contexts_stay_out_of_batches():
-    from paper_2002_03000_amd import ParallelFlatPERM, _abi
-    import torch
-    lib = _abi.load()
+def test_long_contexts_batch_but_do_not_chain():
+    # a long walk (sums in global memory) runs in a batched launch, in a class
+    # of its own, with the bits it gives alone; the chained launch, whose merge
+    # reads the sums from LDS, refuses it
+    from paper_2002_03000_amd import Batch, ParallelFlatPERM, PPermError, run_job
     g = ParallelFlatPERM(2, 9000, 4, 9)
-    ctxs = (ctypes.c_void_p * 1)(g._ctx)
-    tours = (ctypes.c_uint32 * 1)(1)
-    need = ctypes.c_size_t()
-    _abi.check(lib.pperm_batch_workspace_bytes(1, ctypes.byref(need)), "batch bytes")
-    ws = torch.empty(need.value + 256, dtype=torch.uint8, device="cuda")
-    assert lib.pperm_run_batch(ctxs, 1, tours, ctypes.c_void_p(ws.data_ptr()), need.value, None) == -1
+    a = ParallelFlatPERM(2, 9000, 4, 9)
+    with pytest.raises(PPermError, match="EINVAL"):
+        run_job([g], [[1]])
+    Batch(1).run_tours([g], [1])
+    a.run_tours(1)
+    rg, ra = g.records("L"), a.records("L")
+    assert np.array_equal(rg["m"], ra["m"]) and np.array_equal(rg["e"], ra["e"]) and np.array_equal(rg["h"], ra["h"])
+    assert np.array_equal(g.sequence_stats()["digest"], a.sequence_stats()["digest"])
 
 
 def test_log_c10000_agrees_with_the_long_run_value():
