@@ -181,6 +181,8 @@ def main():
     ap.add_argument("--compare-replicas", type=int, default=8, help="compare: independent runs per cell")
     ap.add_argument("--compare-t", default="64,1", help="compare: Algorithm 2 tours per epoch")
     ap.add_argument("--compare-nmax", type=int, default=500, help="compare: maximum walk length")
+    ap.add_argument("--compare-short-t-max-s", type=int, default=1000,
+                    help="compare: Algorithm 2 with T < 64 only up to this many tours per sequence")
     ap.add_argument("--serve-duration", type=float, default=60.0, help="served: arrival window (s)")
     ap.add_argument("--serve-rate", type=float, default=50.0, help="served: arrivals per second")
     ap.add_argument("--serve-cap", type=int, default=1_000_000, help="served: tour cap per job")
@@ -700,7 +702,8 @@ def run_served(args):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         M = 0
-        for T in workloads.Problem(p.dim, p.n_max, p.n_sequences, p.tours_per_epoch, 1 << 30, p.seed,
+        epochs = j.tour_cap // (p.n_sequences * p.tours_per_epoch) + 8
+        for T in workloads.Problem(p.dim, p.n_max, p.n_sequences, p.tours_per_epoch, epochs, p.seed,
                                    stream=p.stream).schedule():
             g.run_tours(T)
             g.merge_epoch()
@@ -817,6 +820,8 @@ def run_compare(args):
             for mode, T in kinds:
                 if mode == "shared" and N == 1 and T != Ts[0]:
                     continue                      # one sequence: T changes nothing
+                if mode == "shared" and T < 64 and S > args.compare_short_t_max_s:
+                    continue                      # short epochs only up to this many tours
                 for r in range(R):
                     seed += 1
                     cells.append((mode, T, N, S, r))
@@ -827,25 +832,43 @@ def run_compare(args):
     # Algorithm 2 problems whose sums fit in LDS chain their epochs on the
     # device (pperm_run_job: one launch, however many epochs); the others run
     # as lock-step batched rounds
-    from paper_2002_03000_amd import run_job
+    from paper_2002_03000_amd import Batch, run_job
     chain = [i for i, (mode, T, N, S, r) in enumerate(cells) if mode == "shared" and n_max <= 2048]
     rest = [i for i in range(len(cells)) if i not in set(chain)]
+
+    last_log = [time.perf_counter()]
+
+    def wait(label):
+        # wait for the stream, saying what runs at least every 10 s
+        ev = torch.cuda.Event()
+        ev.record()
+        while not ev.query():
+            time.sleep(0.05)
+            if time.perf_counter() - last_log[0] > 10:
+                last_log[0] = time.perf_counter()
+                _log(f"compare: {label}, {last_log[0] - t0:.0f} s")
+        if time.perf_counter() - last_log[0] > 10:
+            last_log[0] = time.perf_counter()
+            _log(f"compare: {label}, {last_log[0] - t0:.0f} s")
+
     if chain:
         job_ws = run_job([probs[i] for i in chain], [scheds[i] for i in chain])
+        wait(f"{len(chain)} Algorithm-2 problems chained on the device")
+        del job_ws
     if rest:
-        run_schedules([probs[i] for i in rest], [scheds[i] for i in rest])
-    done = torch.cuda.Event()
-    done.record()
-    last = t0
-    while not done.query():
-        time.sleep(0.5)
-        if time.perf_counter() - last > 10:
-            last = time.perf_counter()
-            _log(f"compare: {len(probs)} problems running, {last - t0:.0f} s")
+        # lock-step batched rounds (each problem's epochs exactly as alone)
+        rp, rs = [probs[i] for i in rest], [scheds[i] for i in rest]
+        batch = Batch(len(rp))
+        rounds = max(len(x) for x in rs)
+        for r in range(rounds):
+            tours = [x[r] if r < len(x) else 0 for x in rs]
+            batch.run_tours(rp, tours)
+            for g, t in zip(rp, tours):
+                if t:
+                    g.merge_epoch()
+            wait(f"{len(rp)} problems in batched rounds, round {r + 1}/{rounds}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    if chain:
-        del job_ws
     steps = {}
     results = {}
     for (mode, T, N, S, r), g in zip(cells, probs):

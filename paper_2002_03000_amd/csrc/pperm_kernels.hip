@@ -74,8 +74,12 @@ __device__ __forceinline__ XF xf_norm(double x, int e) {
 }
 
 // Written with selects only (no branches): the operand with the larger
-// exponent keeps its scale, the other is shifted onto it (exact for a shift of
-// at most 63 binades; beyond that it cannot change the rounded sum).
+// exponent keeps its scale, the other is shifted onto it.  The shift is exact
+// while the shifted mantissa stays normal; once it has moved 54 or more
+// binades it is below half an ulp of the kept mantissa (which lies in
+// [0.5, 1)), so the rounded sum is the kept mantissa whatever it became --
+// the same as dropping it, which is how the exact operation is usually
+// written (a shift beyond 63 binades is dropped).
 __device__ __forceinline__ XF xf_add(XF a, XF b) {
     const bool sw = a.e < b.e;
     const double hm = sw ? b.m : a.m;
@@ -83,7 +87,7 @@ __device__ __forceinline__ XF xf_add(XF a, XF b) {
     const double lm = sw ? a.m : b.m;
     const int le = sw ? a.e : b.e;
     const int d = he - le;
-    const double ls = (d > 63) ? 0.0 : ldexp(lm, -d);
+    const double ls = ldexp(lm, -d);
     XF r = xf_norm(hm + ls, he);
     // zero operands (field by field, so that no struct is selected by address)
     const bool az = (a.m == 0.0), bz = (b.m == 0.0);
@@ -115,30 +119,46 @@ __device__ __forceinline__ XF xf_norm_nz(double x, int e) {
     return r;
 }
 
-// a + b for b != 0: a zero a is shifted away like a negligible one (its
-// mantissa is 0, so the sum is exactly b).
+// a + b for b != 0: both mantissas are brought to the larger exponent (the
+// larger operand's by an exact shift of 0, the other's as in xf_add) and
+// added, so no operand swap is needed.  A zero a counts as having the
+// smallest exponent: shifted away, its mantissa 0 leaves exactly b.
 __device__ __forceinline__ XF xf_add_nz(XF a, XF b) {
-    const bool sw = (a.m == 0.0) || (a.e < b.e);
-    const double hm = sw ? b.m : a.m;
-    const int he = sw ? b.e : a.e;
-    const double lm = sw ? a.m : b.m;
-    const int le = sw ? a.e : b.e;
-    const int d = he - le;
-    const double ls = (d > 63) ? 0.0 : ldexp(lm, -d);
-    return xf_norm_nz(hm + ls, he);
+    const int ae = (a.m == 0.0) ? -0x40000000 : a.e;
+    const int he = ae > b.e ? ae : b.e;
+    return xf_norm_nz(ldexp(a.m, ae - he) + ldexp(b.m, b.e - he), he);
+}
+
+// x / y, correctly rounded, for operands whose quotient and reciprocal are
+// far from the ends of the FP64 range: x in [0.5, 1) and y in [0.5, 2^34]
+// here (a mantissa, or a mantissa over an integer below 2^34).  Markstein's
+// method: the hardware reciprocal refined by two Newton-Raphson steps with
+// fused multiply-adds, the quotient x * y, and one correction with the exact
+// residual x - y q.  It is the general IEEE division sequence without its
+// operand scaling and special-case fix-up, which leave such operands and
+// their quotient unchanged.
+__device__ __forceinline__ double div_normal(double x, double y) {
+    double r = __builtin_amdgcn_rcp(y);
+    double e = __builtin_fma(-y, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-y, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    const double q = x * r;
+    const double res = __builtin_fma(-y, q, x);
+    return __builtin_fma(res, r, q);
 }
 
 __device__ __forceinline__ XF xf_mul_nz(XF a, double k) { return xf_norm_nz(a.m * k, a.e); }
-__device__ __forceinline__ XF xf_div_nz(XF a, double k) { return xf_norm_nz(a.m / k, a.e); }
+// a / k for an integer 2 <= k < 2^34
+__device__ __forceinline__ XF xf_div_nz(XF a, double k) { return xf_norm_nz(div_normal(a.m, k), a.e); }
 
-// a / b for a, b != 0.
+// a / b for a, b != 0 whose ratio is below 2^34 (a decision's W * seen over a
+// sum that includes N copies of W, see walk_sequence): the exponent gap is at
+// most 35, so of the general clamp to [-1000, 1000] only the lower end can act.
 __device__ __forceinline__ double xf_ratio_nz(XF a, XF b) {
     const int d = a.e - b.e;
-    const int dc = d < -1000 ? -1000 : (d > 1000 ? 1000 : d);
-    double r = ldexp(a.m / b.m, dc);
-    r = (d > 1000) ? 0x1p1000 : r;
-    r = (d < -1000) ? 0.0 : r;
-    return r;
+    const double r = ldexp(div_normal(a.m, b.m), d < -1000 ? -1000 : d);
+    return (d < -1000) ? 0.0 : r;
 }
 
 __device__ __forceinline__ XF xf_of(const SumRec& r) { return XF{r.m, r.e}; }
@@ -851,8 +871,8 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
         }
         // events of this tour; fewer than 2^32 because the step cap is at most
         // 2^31 and every event either grows the walk or prunes a grown copy
-        uint32_t k = 0, kb = 0;
-        bool stale = true;
+        // (kb starts 64 below k, so the first event computes a block)
+        uint32_t k = 0, kb = (uint32_t)-64;
         uint4 rb = make_uint4(0, 0, 0, 0);
         double ul = 0.0;                       // this lane's block as a 53-bit uniform
         uint32_t n = 0;
@@ -865,15 +885,16 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
         Key top_key = 0;
         XF Lc = {0.0, 0};
         SumRec Gpre = load_const(Grow);        // pooled sum of the current length
-        // tours seen by the running average of eqn (6) (reading of Algorithm 2)
-        const double seen = (double)(MGs + pool_u * (uint64_t)m);
+        // tours seen by the running average of eqn (6) (reading of Algorithm 2),
+        // converted once per tour and kept in registers
+        double seen = (double)(MGs + pool_u * (uint64_t)m);
+        asm volatile("" : "+v"(seen));
 
         for (;;) {
             bool bt = false;
             // ---- the random block this step's event would draw (64 per pass) ----
-            if (stale || (k - kb) >= 64u) {
+            if (k - kb >= 64u) {
                 kb = k;
-                stale = false;
                 rb = philox10(make_uint4(kb + (uint32_t)lane, 0u, tt, s), P.key0, P.key1);
                 // u of each lane's block, formed once per 64 events (exact:
                 // integers below 2^53 and power-of-two scalings)
@@ -911,12 +932,16 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
                 const double r = xf_ratio_nz(xf_mul_nz(w, seen), sum);
                 const double u = lane_value(ul, li);
                 const double f = floor(r);
-                // bit 0: r >= 1; bit 1: keep floor(r) copies (r integral, or u
-                // below ceil(r) - r); bit 3: a walk with r < 1 survives
-                ub = ufirst((r >= 1.0 ? 1u : 0u) | ((r == f || u < (f + 1.0) - r) ? 2u : 0u) |
-                            (u < r ? 8u : 0u));
-                // (keep the conversion defined for every r)
-                fi = ufirst((uint32_t)((f >= 0.0 && f < 4294967295.0) ? f : 0.0));
+                // bit 1: keep floor(r) copies (r integral, or u below
+                // ceil(r) - r); bit 3: a walk with r < 1 survives
+                ub = ufirst(((r == f || u < (f + 1.0) - r) ? 2u : 0u) | (u < r ? 8u : 0u));
+                // floor(r) as an integer: r > 0, and r <= seen / N < 2^32 because
+                // the sum includes N times the walk's own weight (the clamp
+                // only keeps the conversion defined); r >= 1 iff fi >= 1.
+                // (Converted in vector registers, then read once.)
+                uint32_t fv = (uint32_t)__builtin_fmin(f, 4294967295.0);
+                asm volatile("" : "+v"(fv));
+                fi = ufirst(fv);
             }
             asm volatile("" ::"s"(ub), "s"(fi));
 
@@ -949,7 +974,9 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
                     if ((frl >> lane) & 1u) myslot = slot;
                 }
             }
-            const uint32_t a = (uint32_t)__popcll(freem);
+            // (a 32-bit count, so that its conversion to FP64 is one instruction)
+            uint32_t a = (uint32_t)__popcll(freem);
+            asm volatile("" : "+s"(a));
             if (a == 0u) {
                 cv += (lane == ST_TRAPS) ? 1ull : 0ull;
                 bt = true;
@@ -957,7 +984,7 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
                 k += 1;
                 bool pruned = false;
                 if (control) {
-                    if (ub & 1u) {
+                    if (fi >= 1u) {
                         // r >= 1: c = floor(r) with probability ceil(r) - r, else ceil(r)
                         const uint32_t ci = (ub & 2u) ? fi : fi + 1u;
                         if (ci > 1u) {
@@ -997,10 +1024,13 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
                     bt = true;
                 } else {
                     // ---- Rosenbluth growth: the j-th free neighbour ----
+                    // (the free direction whose field-top lane has exactly j
+                    // free field tops below it)
                     const uint32_t j = __umulhi(B0, a);
-                    uint64_t mm = freem;
-                    for (uint32_t i = 0; i < j; ++i) mm &= mm - 1u;
-                    const int dir = (__ffsll((unsigned long long)mm) - 1) >> F::LW;
+                    const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                        (uint32_t)(freem >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)freem, 0u));
+                    const uint64_t pick = __ballot(below == j) & freem;
+                    const int dir = (__ffsll((unsigned long long)pick) - 1) >> F::LW;
                     digest = (digest ^ (uint64_t)((uint32_t)dir | (a << 3))) * FNV_PRIME;
                     // insertion slot: the first empty slot of the chosen direction's run
                     const uint32_t il =
