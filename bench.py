@@ -825,7 +825,13 @@ def run_compare(args):
                 for r in range(R):
                     seed += 1
                     cells.append((mode, T, N, S, r))
-                    probs.append(ParallelFlatPERM(2, n_max, N, seed, mode=mode, stream_id=len(probs)))
+                    # the same step watchdog per call for every epoch length: the
+                    # default one of a 64-tour epoch (a one-tour epoch's default
+                    # would stop the enrichment cascades short epochs meet at
+                    # rarely reached lengths)
+                    cap = min(2 ** 31 - 1, 4096 * 64 * (n_max + 1))
+                    probs.append(ParallelFlatPERM(2, n_max, N, seed, mode=mode, stream_id=len(probs),
+                                                  step_cap=cap))
                     scheds.append(tour_schedule(S, T))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -869,10 +875,21 @@ def run_compare(args):
             wait(f"{len(rp)} problems in batched rounds, round {r + 1}/{rounds}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    from paper_2002_03000_amd import PPermError
     steps = {}
     results = {}
+    capped = {}
     for (mode, T, N, S, r), g in zip(cells, probs):
-        lc, _, _ = g.estimates()
+        try:
+            lc, _, _ = g.estimates()
+        except PPermError as exc:
+            # a sequence hit the step cap (an enrichment cascade at lengths
+            # no sequence had reached): counted, left out of the tables
+            key = f"{mode} T={T} N={N} S={S}"
+            capped[key] = capped.get(key, 0) + 1
+            _log(f"compare: {key} replica {r}: {exc}")
+            g.close()
+            continue
         if mode == "independent":
             per = g.sequence_log_estimates()
             ests = {"alg1_mean": lc, "alg1_geometric": analysis.combine_geometric(per)}
@@ -911,6 +928,7 @@ def run_compare(args):
                    "reference_fit": ref_fit, "reference_log_c_nmax": float(log_best[n_max]), "replicas": R},
         "tables": table,
         "walk_steps": steps,
+        "stopped_by_step_cap": capped,
         "walk_steps_per_s_all": sum(steps.values()) / elapsed,
         "seconds": elapsed,
     }
