@@ -181,6 +181,8 @@ def main():
     ap.add_argument("--compare-replicas", type=int, default=8, help="compare: independent runs per cell")
     ap.add_argument("--compare-t", default="64,1", help="compare: Algorithm 2 tours per epoch")
     ap.add_argument("--compare-nmax", type=int, default=500, help="compare: maximum walk length")
+    ap.add_argument("--compare-step-cap", type=int, default=0,
+                    help="compare: walk-steps one sequence may take per call (0: that of a 64-tour epoch)")
     ap.add_argument("--compare-short-t-max-s", type=int, default=1000,
                     help="compare: Algorithm 2 with T < 64 only up to this many tours per sequence")
     ap.add_argument("--serve-duration", type=float, default=60.0, help="served: arrival window (s)")
@@ -688,6 +690,10 @@ def run_served(args):
     srv.close()
     gpu_ms = sum(a.elapsed_time(b) for a, b in step_events)
     value = steps_done / elapsed
+    _log(f"served: {len(jobs)} jobs, {steps_done} walk-steps in {elapsed:.1f} s = {value:.3e} walk-steps/s, "
+         f"latency p50 {np.nanpercentile(lat, 50):.1f} s p99 {np.nanpercentile(lat, 99):.1f} s, "
+         f"{n_steps} server steps, {active_sum / max(1, n_steps):.1f} jobs active on average, "
+         f"stops {stops}, GPU busy {gpu_ms / 1e3 / elapsed:.3f}")
 
     # the plain path on the same jobs: each job alone through pperm_run_tours /
     # pperm_merge_epoch, its stop rule checked on the host after every merge
@@ -828,8 +834,9 @@ def run_compare(args):
                     # the same step watchdog per call for every epoch length: the
                     # default one of a 64-tour epoch (a one-tour epoch's default
                     # would stop the enrichment cascades short epochs meet at
-                    # rarely reached lengths)
-                    cap = min(2 ** 31 - 1, 4096 * 64 * (n_max + 1))
+                    # rarely reached lengths), or a smaller one that bounds the
+                    # run's time at long n_max
+                    cap = args.compare_step_cap or min(2 ** 31 - 1, 4096 * 64 * (n_max + 1))
                     probs.append(ParallelFlatPERM(2, n_max, N, seed, mode=mode, stream_id=len(probs),
                                                   step_cap=cap))
                     scheds.append(tour_schedule(S, T))
@@ -929,6 +936,7 @@ def run_compare(args):
         "tables": table,
         "walk_steps": steps,
         "stopped_by_step_cap": capped,
+        "step_cap_per_call": args.compare_step_cap or min(2 ** 31 - 1, 4096 * 64 * (n_max + 1)),
         "walk_steps_per_s_all": sum(steps.values()) / elapsed,
         "seconds": elapsed,
     }

@@ -117,3 +117,38 @@ def test_sums_in_global_memory_change_no_bit(dim, n_max, N, seed):
         assert_pooled_equal(g, o, "sums in global memory")
     a, b = g.sequence_stats(), h.sequence_stats()
     assert all(np.array_equal(a[f], b[f]) for f in a.dtype.names)
+
+
+def test_global_sums_walker_independent_and_rosenbluth_batched():
+    # Algorithm 1 (each sequence with its own sums) and plain Rosenbluth runs
+    # through the walker that keeps the sums in global memory, in one batched
+    # launch with one-tour and longer epochs: each problem bit-identical to the
+    # oracle.  Each sequence of Algorithm 1 meets its own enrichment cascade on
+    # its second tour, so every context gets the step watchdog of a 64-tour
+    # epoch.
+    from paper_2002_03000_amd import Batch, ParallelFlatPERM
+    specs = [(2, 700, 5, 31, "independent"), (3, 500, 4, 32, "independent"),
+             (2, 600, 6, 33, "rosenbluth"), (3, 300, 7, 34, "shared")]
+    gs = [ParallelFlatPERM(d, n, N, sd, mode=mode, stream_id=i, sums_global=True,
+                           step_cap=4096 * 64 * (n + 1))
+          for i, (d, n, N, sd, mode) in enumerate(specs)]
+    os_ = [oracle.Oracle(d, n, N, sd, mode={"shared": 0, "independent": 1, "rosenbluth": 2}[mode], stream=i)
+           for i, (d, n, N, sd, mode) in enumerate(specs)]
+    b = Batch(len(specs))
+    for e, tours in enumerate(([1, 1, 1, 1], [1, 1, 2, 1], [2, 1, 1, 2], [4, 2, 0, 4])):
+        print(f"global-sums batch epoch {e}: tours {tours}", flush=True)
+        b.run_tours(gs, tours)
+        for i, (g, o, t) in enumerate(zip(gs, os_, tours)):
+            if not t:
+                continue
+            assert not o.run_tours(t)
+            assert_epoch_equal(g, o, label=f"global sums problem {i} ({specs[i][4]}) epoch {e}")
+            g.merge_epoch()
+            o.merge_epoch()
+            assert_pooled_equal(g, o, f"global sums problem {i} merge {e}")
+    for g, o in zip(gs, os_):
+        lc, _, _ = g.estimates()
+        olc = o.log_estimates()
+        fin = np.isfinite(olc)
+        assert np.array_equal(fin, np.isfinite(lc))
+        np.testing.assert_allclose(lc[fin], olc[fin], rtol=1e-12, atol=0)
