@@ -790,12 +790,12 @@ def run_compare(args):
     eqn (9) against a longer reference run of Algorithm 2, the band width E of
     the eqn-(16) fit, and log c_{n_max}, for N sequences and S tours per
     sequence (the layout of the paper's Tables 1-4 at --compare-nmax 10000).
-    Every cell is --compare-replicas independent problems; all of them run
-    together as lock-step batched rounds (each problem's epochs exactly as
-    alone, long walks in classes of their own)."""
+    Every cell is --compare-replicas independent runs; all of them chain their
+    epochs on the device in one launch, each at its own pace (each problem's
+    epochs exactly as alone)."""
     import numpy as np
     import torch
-    from paper_2002_03000_amd import ParallelFlatPERM, analysis, run_schedules
+    from paper_2002_03000_amd import ParallelFlatPERM, analysis
 
     torch.cuda.set_device(0)
     n_max = args.compare_nmax
@@ -818,6 +818,15 @@ def run_compare(args):
     Ss = [int(x) for x in args.compare_s.split(",")]
     Ts = [int(x) for x in args.compare_t.split(",")]
     R = args.compare_replicas
+    # the same step watchdog per call for every epoch length: the default one
+    # of a 64-tour epoch (a one-tour epoch's default would stop the enrichment
+    # cascades short epochs meet at rarely reached lengths), or a smaller one
+    # that bounds the run's time at long n_max
+    cap = args.compare_step_cap or min(2 ** 31 - 1, 4096 * 64 * (n_max + 1))
+    # cells: (mode, T, N, S, replica, indices of its problems).  Algorithm 1's N
+    # independent sequences are N one-sequence problems (a flatPERM sequence
+    # alone; with one sequence the epoch length changes nothing but rounding
+    # order), Algorithm 2 is one problem of N sequences
     cells, probs, scheds = [], [], []
     seed = 910_000
     for N in Ns:
@@ -830,25 +839,17 @@ def run_compare(args):
                     continue                      # short epochs only up to this many tours
                 for r in range(R):
                     seed += 1
-                    cells.append((mode, T, N, S, r))
-                    # the same step watchdog per call for every epoch length: the
-                    # default one of a 64-tour epoch (a one-tour epoch's default
-                    # would stop the enrichment cascades short epochs meet at
-                    # rarely reached lengths), or a smaller one that bounds the
-                    # run's time at long n_max
-                    cap = args.compare_step_cap or min(2 ** 31 - 1, 4096 * 64 * (n_max + 1))
-                    probs.append(ParallelFlatPERM(2, n_max, N, seed, mode=mode, stream_id=len(probs),
-                                                  step_cap=cap))
-                    scheds.append(tour_schedule(S, T))
+                    members = N if mode == "independent" else 1
+                    idx = []
+                    for _ in range(members):
+                        idx.append(len(probs))
+                        probs.append(ParallelFlatPERM(2, n_max, 1 if mode == "independent" else N, seed,
+                                                      mode="shared", stream_id=len(probs), step_cap=cap))
+                        scheds.append(tour_schedule(S, T))
+                    cells.append((mode, T, N, S, r, idx))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    # Algorithm 2 problems whose sums fit in LDS chain their epochs on the
-    # device (pperm_run_job: one launch, however many epochs); the others run
-    # as lock-step batched rounds
-    from paper_2002_03000_amd import Batch, run_job
-    chain = [i for i, (mode, T, N, S, r) in enumerate(cells) if mode == "shared" and n_max <= 2048]
-    rest = [i for i in range(len(cells)) if i not in set(chain)]
-
+    from paper_2002_03000_amd import run_job, job_report
     last_log = [time.perf_counter()]
 
     def wait(label):
@@ -860,56 +861,42 @@ def run_compare(args):
             if time.perf_counter() - last_log[0] > 10:
                 last_log[0] = time.perf_counter()
                 _log(f"compare: {label}, {last_log[0] - t0:.0f} s")
-        if time.perf_counter() - last_log[0] > 10:
-            last_log[0] = time.perf_counter()
-            _log(f"compare: {label}, {last_log[0] - t0:.0f} s")
 
-    if chain:
-        job_ws = run_job([probs[i] for i in chain], [scheds[i] for i in chain])
-        wait(f"{len(chain)} Algorithm-2 problems chained on the device")
-        del job_ws
-    if rest:
-        # lock-step batched rounds (each problem's epochs exactly as alone)
-        rp, rs = [probs[i] for i in rest], [scheds[i] for i in rest]
-        batch = Batch(len(rp))
-        rounds = max(len(x) for x in rs)
-        for r in range(rounds):
-            tours = [x[r] if r < len(x) else 0 for x in rs]
-            batch.run_tours(rp, tours)
-            for g, t in zip(rp, tours):
-                if t:
-                    g.merge_epoch()
-            wait(f"{len(rp)} problems in batched rounds, round {r + 1}/{rounds}")
+    # every problem chains its epochs on the device, each at its own pace
+    job_ws = run_job(probs, scheds)
+    wait(f"{len(probs)} problems chained on the device")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    report = job_report(job_ws)
+    del job_ws
     from paper_2002_03000_amd import PPermError
     steps = {}
     results = {}
     capped = {}
-    for (mode, T, N, S, r), g in zip(cells, probs):
+    for (mode, T, N, S, r, idx) in cells:
+        key = f"{mode} T={T} N={N} S={S}"
         try:
-            lc, _, _ = g.estimates()
+            lcs = [probs[i].estimates()[0] for i in idx]
         except PPermError as exc:
             # a sequence hit the step cap (an enrichment cascade at lengths
             # no sequence had reached): counted, left out of the tables
-            key = f"{mode} T={T} N={N} S={S}"
             capped[key] = capped.get(key, 0) + 1
             _log(f"compare: {key} replica {r}: {exc}")
-            g.close()
             continue
+        st = sum(probs[i].stats()["steps"] for i in idx)
         if mode == "independent":
-            per = g.sequence_log_estimates()
-            ests = {"alg1_mean": lc, "alg1_geometric": analysis.combine_geometric(per)}
-            steps["alg1"] = steps.get("alg1", 0) + g.stats()["steps"]
+            ests = {"alg1_mean": analysis.combine_mean(lcs), "alg1_geometric": analysis.combine_geometric(lcs)}
+            steps["alg1"] = steps.get("alg1", 0) + st
         else:
-            ests = {f"alg2_T{T}": lc}
-            steps[f"alg2_T{T}"] = steps.get(f"alg2_T{T}", 0) + g.stats()["steps"]
+            ests = {f"alg2_T{T}": lcs[0]}
+            steps[f"alg2_T{T}"] = steps.get(f"alg2_T{T}", 0) + st
         for kind, est in ests.items():
             fin = np.isfinite(est)
             top = int(np.max(np.nonzero(fin)[0])) if fin.any() else 0
             tm = analysis.total_abs_error(log_best, est, M=top) if top > 0 else float("nan")
             e = analysis.ratio_fit(est, n_max=top)["E"] if top > 3 else float("nan")
             results.setdefault((kind, N, S), []).append((tm, e, top, est[n_max]))
+    for g in probs:
         g.close()
     table = {"T_M": {}, "T_M_se": {}, "E": {}, "E_se": {}, "log_c_nmax": {}, "log_c_nmax_se": {},
              "sampled_lengths_min": {}}
@@ -936,7 +923,8 @@ def run_compare(args):
         "tables": table,
         "walk_steps": steps,
         "stopped_by_step_cap": capped,
-        "step_cap_per_call": args.compare_step_cap or min(2 ** 31 - 1, 4096 * 64 * (n_max + 1)),
+        "step_cap_per_call": cap,
+        "job_report": report,
         "walk_steps_per_s_all": sum(steps.values()) / elapsed,
         "seconds": elapsed,
     }

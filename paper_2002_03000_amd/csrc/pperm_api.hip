@@ -120,15 +120,14 @@ int resolve_shape(const pperm_config* c, Shape* sh) {
     bool lng = false;
     uint64_t bytes;
     if (wpw == 1) {
-        bytes = (uint64_t)team_bytes(slots) + row_bytes * (obs ? 2u : 1u) +
-                LDS_STACK * (uint32_t)sizeof(StackEntry);
+        bytes = (uint64_t)team_bytes(slots) + row_bytes * (obs ? 2u : 1u);
         if (bytes > kLdsLimit || force_global) {
             lng = true;
             if (c->hash_slots == 0)
-                while (team_bytes(slots) + LDS_STACK * sizeof(StackEntry) > kLdsLimit &&
+                while (team_bytes(slots) > kLdsLimit &&
                        5u * (slots / 2u) >= 8u * n1)
                     slots >>= 1;
-            bytes = (uint64_t)team_bytes(slots) + LDS_STACK * (uint32_t)sizeof(StackEntry);
+            bytes = (uint64_t)team_bytes(slots);
         }
     } else {
         bytes = (uint64_t)team_bytes(slots) * wpw;
@@ -557,10 +556,9 @@ int plan_batch(pperm_ctx* const* ctxs, size_t count, const uint32_t* tours_each,
         const uint64_t pooled = (x->cfg.mode == PPERM_SHARED) ? x->merged_tours + N * per_seq_total
                                                               : x->merged_tours + per_seq_total;
         if (pooled > 0xFFFFFFFFull || per_seq_total > 0xFFFFFFFFull) return PPERM_EOVERFLOW;
-        // LDS of one walk: occupancy table and slot ids, the sequence's sums
-        // (unless they stay in global memory), the bottom of the copy stack
-        const uint32_t lds = x->desc.lds_team_bytes + (x->long_walk ? 0u : x->desc.row * (uint32_t)sizeof(SumRec)) +
-                             LDS_STACK * (uint32_t)sizeof(StackEntry);
+        // LDS of one walk: occupancy table and slot ids, and the sequence's
+        // sums unless they stay in global memory
+        const uint32_t lds = x->desc.lds_team_bytes + (x->long_walk ? 0u : x->desc.row * (uint32_t)sizeof(SumRec));
         items.push_back({x, tours_each[i], lds,
                          (double)N * tours_each[i] * (double)(x->cfg.n_max + 1), x->long_walk});
     }
@@ -783,8 +781,7 @@ extern "C" int pperm_epoch_graph_destroy(pperm_graph* G) {
 namespace {
 
 uint32_t lds_of(const pperm_ctx* x) {
-    return x->desc.lds_team_bytes + x->desc.row * (uint32_t)sizeof(SumRec) +
-           LDS_STACK * (uint32_t)sizeof(StackEntry);
+    return x->desc.lds_team_bytes + (x->long_walk ? 0u : x->desc.row * (uint32_t)sizeof(SumRec));
 }
 
 uint32_t pow2_at_least(uint32_t n) {
@@ -837,7 +834,7 @@ int job_validate(pperm_ctx* const* ctxs, const uint32_t* const* schedules, const
         pperm_ctx* x = ctxs[i];
         if (!x || x->device != device || x->team_lanes != 64) return PPERM_EINVAL;
         if (x->cfg.mode == PPERM_INDEPENDENT) return PPERM_EINVAL;
-        if ((x->cfg.flags & PPERM_FLAG_OBSERVABLES) || x->long_walk) return PPERM_EINVAL;
+        if (x->cfg.flags & PPERM_FLAG_OBSERVABLES) return PPERM_EINVAL;
         for (size_t j = 0; j < i; ++j)
             if (ctxs[j] == x) return PPERM_EINVAL;
         if (x->open_tours != 0) return PPERM_ESTATE;
@@ -889,9 +886,10 @@ int run_job_impl(pperm_ctx* const* ctxs, const uint32_t* const* schedules, const
     hipStream_t stream = (hipStream_t)hip_stream;
     unsigned char* ws = (unsigned char*)d_workspace;
 
-    // LDS classes (powers of two from 8 KB, at most four: the smallest fold
-    // upwards), then the order in which waves look for work: classes from
-    // the largest, inside a class the longest chain of steps first
+    // LDS classes (bounds at powers of two from 8 KB, at most four: the
+    // smallest fold upwards; each class launched with the largest LDS one of
+    // its problems needs), then the order in which waves look for work:
+    // classes from the largest, inside a class the longest chain of steps first
     std::vector<uint32_t> cls_lds;
     std::vector<uint32_t> pcls(count, 0);
     {
@@ -905,13 +903,14 @@ int run_job_impl(pperm_ctx* const* ctxs, const uint32_t* const* schedules, const
         std::sort(sizes.begin(), sizes.end());
         sizes.erase(std::unique(sizes.begin(), sizes.end()), sizes.end());
         while (sizes.size() > (size_t)kBatchStreams) sizes.erase(sizes.begin());
-        cls_lds = sizes;
+        cls_lds.assign(sizes.size(), 0u);
         for (size_t i = 0; i < count; ++i) {
             if (!epochs[i]) continue;
             const uint32_t need = lds_of(ctxs[i]);
             uint32_t c = 0;
-            while (cls_lds[c] < need) ++c;
+            while (sizes[c] < need) ++c;
             pcls[i] = c;
+            cls_lds[c] = std::max(cls_lds[c], need);
         }
     }
     if (cls_lds.empty()) return PPERM_OK;               // no epochs at all
@@ -960,6 +959,7 @@ int run_job_impl(pperm_ctx* const* ctxs, const uint32_t* const* schedules, const
         J.levels = log2u(J.p2);
         J.cls = pcls[i];
         J.lds = lds_of(x);
+        J.lng = x->long_walk ? 1u : 0u;
         J.result = reinterpret_cast<uint32_t*>(ws + L.results) + 4 * i;
         if (limits) {
             J.stage = reinterpret_cast<SumRec*>(ws + L.stage[i]);

@@ -27,10 +27,7 @@ enum : uint32_t { MODE_SHARED = 0, MODE_INDEPENDENT = 1, MODE_ROSENBLUTH = 2 };
 constexpr uint32_t COMPACT3_MAX_N = 1022;
 
 constexpr int STATS_WORDS = 10;
-constexpr uint32_t GROUPS = 16;
-// Copy-stack entries kept in LDS per wave-per-walk sequence (positions
-// 0 .. LDS_STACK-1 from the bottom; deeper ones live in global memory).
-constexpr uint32_t LDS_STACK = 32;   // sequence groups of the error estimate (s mod 16)
+constexpr uint32_t GROUPS = 16;   // sequence groups of the error estimate (s mod 16)
 enum : int { ST_STEPS = 0, ST_EVENTS, ST_ENRICH, ST_COPIES, ST_PRUNES, ST_TRAPS,
              ST_TOURS, ST_MAXDEPTH, ST_DIGEST, ST_CAPPED };
 
@@ -151,7 +148,7 @@ struct JobProblem {
     uint32_t cls;             // LDS class
     uint32_t lds;             // LDS bytes its walks need
     uint32_t prio;            // issue priority 0..3 of its waves (longest chains highest)
-    uint32_t pad;
+    uint32_t lng;             // 1: long walks, the sequences' sums live in global memory
     // stop rule (evaluated after every merge; stage == nullptr: none)
     SumRec* stage;            // [N] each sequence's record at n_max in the open epoch
     uint32_t* stage_m;        // [N] its tours in the open epoch

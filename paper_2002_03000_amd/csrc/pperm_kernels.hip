@@ -755,18 +755,16 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
     constexpr int W = F::W;                    // probe positions per direction per window
     constexpr uint32_t FIELD = (1u << W) - 1u;
 
-    // LDS: the occupancy table, the slot id of every site of the walk, the
+    // LDS: the occupancy table, the slot id of every site of the walk and the
     // sequence's own per-length sums (moved in at the start of the sequence's
-    // tours and back out at their end) and the bottom of its copy stack
+    // tours and back out at their end)
     Key* table = reinterpret_cast<Key*>(lds);
     uint16_t* sid = reinterpret_cast<uint16_t*>(lds + (sizeof(Key) << P.slots_log2));
     const uint32_t row_lds = LONG ? 0u : P.row * (uint32_t)sizeof(SumRec);
     SumRec* Ls = LONG ? P.L + (size_t)s * P.row : reinterpret_cast<SumRec*>(lds + P.lds_team_bytes);
-    StackEntry* lstk = reinterpret_cast<StackEntry*>(lds + P.lds_team_bytes + row_lds);
-    // (observables) the sequence's per-length sums of W * R^2, after the stack
+    // (observables) the sequence's per-length sums of W * R^2, after its sums
     SumRec* LRs = LONG ? P.LR + (size_t)s * P.row
-                       : reinterpret_cast<SumRec*>(lds + P.lds_team_bytes + row_lds +
-                                                   LDS_STACK * sizeof(StackEntry));
+                       : reinterpret_cast<SumRec*>(lds + P.lds_team_bytes + row_lds);
     // record access: LDS, or the global row of a long walk
     auto rec_ld = [&](const SumRec* p) -> SumRec {
         if constexpr (LONG) return load_global(p);
@@ -855,6 +853,11 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
     uint64_t cv = 0;
     uint64_t digest = ufirst64(P.stats[(size_t)s * STATS_WORDS + ST_DIGEST]);
     bool abort = false;
+    // the registers of the copy stack (see the tour loop)
+    uint32_t cs_n = 0u, cs_rem = 0u;
+    int32_t cs_e = 0;
+    double cs_m = 0.0;
+    Key cs_key = (Key)0;
 
     for (uint32_t tour = 0; tour < tours && !abort; ++tour) {
         // ---- a pass through the empty walk (eqn (4), M) ----
@@ -878,11 +881,10 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
         uint32_t n = 0;
         Key ekey = origin_key;                 // the walk's end
         uint32_t control = 0u;                 // a decision is due at this length
-        // pending copies: the top entry in scalar registers, the others at
-        // positions 0 .. sp-2 (LDS below LDS_STACK, global memory above)
-        uint32_t sp = 0, top_n = 0, top_rem = 0;
-        XF top_w = {0.0, 0};
-        Key top_key = 0;
+        // pending copies: sp entries, the one at position p in lane p mod 64
+        // of the cs_* registers for p >= lo, in global memory for p < lo (at
+        // most 64 in registers; the most recent ones, which are resumed first)
+        uint32_t sp = 0, lo = 0;
         XF Lc = {0.0, 0};
         SumRec Gpre = load_const(Grow);        // pooled sum of the current length
         // tours seen by the running average of eqn (6) (reading of Algorithm 2),
@@ -989,25 +991,28 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
                         const uint32_t ci = (ub & 2u) ? fi : fi + 1u;
                         if (ci > 1u) {
                             w = xf_div_nz(w, (double)ci);
-                            if (sp > 0u) {
-                                // the old top goes to position sp - 1
-                                StackEntry e;
-                                e.n = top_n;
-                                e.remaining = top_rem;
-                                e.e = top_w.e;
-                                e.pad0 = 0u;
-                                e.m = top_w.m;
-                                e.key = (uint64_t)top_key;
-                                if (sp - 1u < LDS_STACK) {
-                                    if (lane == 0) lstk[sp - 1u] = e;
-                                } else {
-                                    store_global(stk + (sp - 1u), e);
+                            if (sp - lo == 64u) {
+                                // every lane holds an entry: the oldest one moves
+                                // to its place in global memory
+                                if (lane == (int)(lo & 63u)) {
+                                    StackEntry e;
+                                    e.n = cs_n;
+                                    e.remaining = cs_rem;
+                                    e.e = cs_e;
+                                    e.pad0 = 0u;
+                                    e.m = cs_m;
+                                    e.key = (uint64_t)cs_key;
+                                    store_global(stk + lo, e);
                                 }
+                                lo += 1u;
                             }
-                            top_n = n;
-                            top_rem = ci - 1u;
-                            top_w = w;
-                            top_key = ekey;
+                            // the new entry: ci - 1 copies still to resume at (n, W / ci)
+                            const bool mine = lane == (int)(sp & 63u);
+                            cs_n = mine ? n : cs_n;
+                            cs_rem = mine ? ci - 1u : cs_rem;
+                            cs_e = mine ? w.e : cs_e;
+                            cs_m = mine ? w.m : cs_m;
+                            cs_key = mine ? ekey : cs_key;
                             sp += 1;
                             c_maxd = (sp > c_maxd) ? sp : c_maxd;
                             cv += (lane == ST_ENRICH) ? 1ull
@@ -1085,21 +1090,28 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
             if (bt) {
                 // ---- resume the most recent pending copy, or end the tour ----
                 if (sp == 0u) break;
-                const uint32_t rn = top_n;
-                w = top_w;
-                ekey = top_key;
-                top_rem -= 1u;
-                if (top_rem == 0u) {
-                    sp -= 1u;
-                    if (sp > 0u) {
-                        const StackEntry e = (sp - 1u < LDS_STACK) ? lstk[sp - 1u]
-                                                                    : load_global(stk + (sp - 1u));
-                        top_n = ufirst(e.n);
-                        top_rem = ufirst(e.remaining);
-                        top_w = XF{e.m, e.e};
-                        top_key = (Key)ufirst64(e.key);
+                if (sp == lo) {
+                    // no pending entry in registers: bring back the most recent
+                    // ones (up to 64) from global memory
+                    const uint32_t base = sp > 64u ? sp - 64u : 0u;
+                    const uint32_t q = base + (((uint32_t)lane - base) & 63u);
+                    if (q < sp) {
+                        const StackEntry e = load_global(stk + q);
+                        cs_n = e.n;
+                        cs_rem = e.remaining;
+                        cs_e = e.e;
+                        cs_m = e.m;
+                        cs_key = (Key)e.key;
                     }
+                    lo = base;
                 }
+                const uint32_t tl = (sp - 1u) & 63u;
+                const uint32_t rn = lane_value(cs_n, tl);
+                const uint32_t rem = lane_value(cs_rem, tl);
+                w = XF{lane_value(cs_m, tl), (int32_t)lane_value((uint32_t)cs_e, tl)};
+                ekey = (Key)lane_value(cs_key, tl);
+                if (rem == 1u) sp -= 1u;       // its last copy: the entry is done
+                else cs_rem -= (lane == (int)tl) ? 1u : 0u;
                 // LIFO deletion of sites rn+1..n restores the table exactly
                 for (uint32_t i = rn + 1u + (uint32_t)lane; i <= n; i += 64u) table[sid[i]] = (Key)0;
                 n = rn;
@@ -1224,7 +1236,9 @@ __device__ void job_merge(const JobArgs& A, const JobProblem& J, const ProblemDe
                           uint32_t e, uint32_t s, uint32_t tours_run, unsigned char* lds) {
     const int lane = (int)threadIdx.x;
     const uint32_t row = P.row, n1 = P.n_max + 1u;
-    const SumRec* Ls = reinterpret_cast<const SumRec*>(lds + P.lds_team_bytes);
+    // the sequence's sums of this epoch: in LDS, or (long walks) its global row,
+    // written by this same wave
+    const SumRec* Ls = J.lng ? P.L + (size_t)s * row : reinterpret_cast<const SumRec*>(lds + P.lds_team_bytes);
     for (uint32_t n = (uint32_t)lane; n < n1; n += 64u)
         __hip_atomic_fetch_add(&P.HG[n], (uint64_t)Ls[n].h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (lane == 0) {
@@ -1457,9 +1471,15 @@ __global__ void __launch_bounds__(64) job_kernel(JobArgs A) {
         uint64_t cap64 = P.step_cap ? (uint64_t)P.step_cap : 4096ull * tours * (P.n_max + 1ull);
         const uint32_t cap = cap64 > (1ull << 31) ? (1u << 31) : (uint32_t)cap64;
         const SumRec* Gsrc = (e == 0u) ? P.G : J.gver + (size_t)(e - 1u) * (P.row + JOB_GAP);
-        const uint32_t rv = (P.dim == 2) ? walk_sequence<2>(P, tours, cap, s, lds, Gsrc, true)
-                            : P.ckey     ? walk_sequence<3, false, false, true>(P, tours, cap, s, lds, Gsrc, true)
-                                         : walk_sequence<3>(P, tours, cap, s, lds, Gsrc, true);
+        uint32_t rv;
+        if (J.lng)
+            rv = (P.dim == 2) ? walk_sequence<2, false, true>(P, tours, cap, s, lds, Gsrc, true)
+                 : P.ckey     ? walk_sequence<3, false, true, true>(P, tours, cap, s, lds, Gsrc, true)
+                              : walk_sequence<3, false, true>(P, tours, cap, s, lds, Gsrc, true);
+        else
+            rv = (P.dim == 2) ? walk_sequence<2>(P, tours, cap, s, lds, Gsrc, true)
+                 : P.ckey     ? walk_sequence<3, false, false, true>(P, tours, cap, s, lds, Gsrc, true)
+                              : walk_sequence<3>(P, tours, cap, s, lds, Gsrc, true);
         if ((rv & WALK_ABORTED) && lane == 0)
             __hip_atomic_fetch_or(&A.state[pi].failed, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         job_merge(A, J, P, pi, e, s, rv & ~WALK_ABORTED, lds);

@@ -127,7 +127,7 @@ def test_server_pool_allocator_first_fit_and_coalescing(seed):
     assert used2 == cap and offs2[-1] == 0
 
 
-@pytest.mark.parametrize("dim,n_max,ok", [(2, 5000, True), (2, 10000, True), (2, 15000, True), (2, 16000, False),
+@pytest.mark.parametrize("dim,n_max,ok", [(2, 5000, True), (2, 10000, True), (2, 16383, True), (2, 16384, False),
                                           (3, 10000, True), (3, 10239, True), (3, 10240, False)])
 def test_long_walk_limits(dim, n_max, ok):
     # walks whose per-length sums no longer fit in LDS beside the occupancy

@@ -64,20 +64,46 @@ def test_long_walk_observables_match_oracle():
     assert np.array_equal(a[~nan].view(np.uint64), b[~nan].view(np.uint64))
 
 
-def test_long_contexts_batch_but_do_not_chain():
+def test_long_contexts_batch_and_chain():
     # a long walk (sums in global memory) runs in a batched launch, in a class
-    # of its own, with the bits it gives alone; the chained launch, whose merge
-    # reads the sums from LDS, refuses it
-    from paper_2002_03000_amd import Batch, ParallelFlatPERM, PPermError, run_job
+    # of its own, and in the chained launch beside in-LDS problems, with the
+    # bits it gives alone epoch by epoch, and the oracle's
+    from paper_2002_03000_amd import Batch, ParallelFlatPERM, job_report, run_job
     g = ParallelFlatPERM(2, 9000, 4, 9)
     a = ParallelFlatPERM(2, 9000, 4, 9)
-    with pytest.raises(PPermError, match="EINVAL"):
-        run_job([g], [[1]])
     Batch(1).run_tours([g], [1])
     a.run_tours(1)
     rg, ra = g.records("L"), a.records("L")
     assert np.array_equal(rg["m"], ra["m"]) and np.array_equal(rg["e"], ra["e"]) and np.array_equal(rg["h"], ra["h"])
     assert np.array_equal(g.sequence_stats()["digest"], a.sequence_stats()["digest"])
+
+    # chained: a long square walk, a long cubic walk with sums in global memory
+    # by choice, and an in-LDS problem (the long square walk stops before the
+    # epoch whose enrichment cascade would pass the default step cap)
+    specs = [(2, 7000, 3, 91, False), (3, 600, 5, 92, True), (2, 200, 20, 93, False)]
+    sched = [[1, 1, 2, 4], [1, 1, 2], [1, 2, 4]]
+    chained = [ParallelFlatPERM(d, n, N, sd, stream_id=i, sums_global=sg) for i, (d, n, N, sd, sg) in enumerate(specs)]
+    alone = [ParallelFlatPERM(d, n, N, sd, stream_id=i, sums_global=sg) for i, (d, n, N, sd, sg) in enumerate(specs)]
+    ws = run_job(chained, sched)
+    rep = job_report(ws)
+    print(f"chained with long walks: {rep}", flush=True)
+    assert rep["problems_finished"] == len(specs) and rep["problems_failed"] == 0 and rep["problems_incomplete"] == 0
+    for i, (x, y) in enumerate(zip(chained, alone)):
+        for T in sched[i]:
+            y.run_tours(T)
+            y.merge_epoch()
+        lx, hx, mx = x.estimates()
+        ly, hy, my = y.estimates()
+        assert mx == my and np.array_equal(hx, hy), f"problem {i}"
+        assert np.array_equal(lx.view(np.uint64), ly.view(np.uint64)), f"problem {i}: chained != alone"
+        a_, b_ = x.sequence_stats(), y.sequence_stats()
+        assert all(np.array_equal(a_[f], b_[f]) for f in a_.dtype.names), f"problem {i}: stats"
+    d, n, N, sd, sg = specs[0]
+    o = oracle.Oracle(d, n, N, sd, stream=0)
+    for T in sched[0]:
+        assert not o.run_tours(T)
+        o.merge_epoch()
+    assert_pooled_equal(chained[0], o, "chained long walk")
 
 
 def test_log_c10000_agrees_with_the_long_run_value():
