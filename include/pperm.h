@@ -62,7 +62,9 @@ typedef struct pperm_config {
     uint32_t mode;            /* PPERM_SHARED / PPERM_INDEPENDENT / PPERM_ROSENBLUTH      */
     uint32_t stream_id;       /* xored into the key's high word; distinct problems of one
                                  batch use distinct ids                                   */
-    uint32_t hash_slots;      /* per-walk occupancy table size (power of two), 0 = auto   */
+    uint32_t hash_slots;      /* per-walk occupancy table size, 0 = auto: a power of two,
+                                 or (one walk per wave) 3 * 2^k; at least 2 (n_max + 1),
+                                 or 1.5 (n_max + 1) where the sums stay in global memory */
     uint32_t walks_per_wave;  /* walks sharing one 64-lane wavefront, 0 = auto            */
     uint32_t step_cap;        /* growth steps per sequence per pperm_run_tours call after
                                  which the sequence stops with PPERM_EOVERFLOW; 0 = the

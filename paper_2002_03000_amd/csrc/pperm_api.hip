@@ -26,7 +26,8 @@ struct pperm_ctx {
     pperm_layout lay;
     int device;
     uint32_t team_lanes;      // TS: lanes per walk
-    uint32_t slots_log2;
+    uint32_t slots_log2;      // (several walks per wave: slots are a power of two)
+    uint32_t slots;
     uint32_t lds_team_bytes;
     uint32_t lds_wg_bytes;
     uint32_t workgroups;
@@ -96,8 +97,9 @@ struct Shape {
 // LDS beside the table and the bottom of its copy stack.  Where that does not
 // fit (walks of several thousand steps), or where PPERM_FLAG_SUMS_GLOBAL asks
 // for more walks per compute unit, the sums stay in global memory and
-// the table may fill up to 5/8 (a power of two of at least 1.6 (n_max + 1)
-// slots) so that table and slot ids of walks up to ~10^4 steps fit in LDS.
+// the table may fill up to 2/3 (at least 1.5 (n_max + 1) slots) so that table
+// and slot ids of walks up to ~10^4 steps fit in LDS.  A walk that has a wave
+// of its own may also use 1.5 times a power of two slots (hash_slots).
 int resolve_shape(const pperm_config* c, Shape* sh) {
     const uint64_t n1 = c->n_max + 1u;
     const uint32_t row_bytes = (uint32_t)align_up(n1, 16) * 16u;
@@ -116,7 +118,10 @@ int resolve_shape(const pperm_config* c, Shape* sh) {
         slots = 64;
         while (slots < 2u * n1) slots <<= 1;
     }
-    if (!is_pow2((uint32_t)slots) || slots > kMaxSlots) return PPERM_EINVAL;
+    // a power of two, or (one walk per wave) 3 * 2^k
+    const bool three = slots >= 96 && slots % 3u == 0 && is_pow2((uint32_t)(slots / 3u));
+    if (!(is_pow2((uint32_t)slots) || (three && wpw == 1)) || slots < 64 || slots > kMaxSlots)
+        return PPERM_EINVAL;
     bool lng = false;
     uint64_t bytes;
     if (wpw == 1) {
@@ -125,14 +130,14 @@ int resolve_shape(const pperm_config* c, Shape* sh) {
             lng = true;
             if (c->hash_slots == 0)
                 while (team_bytes(slots) > kLdsLimit &&
-                       5u * (slots / 2u) >= 8u * n1)
+                       2u * (slots / 2u) >= 3u * n1)
                     slots >>= 1;
             bytes = (uint64_t)team_bytes(slots);
         }
     } else {
         bytes = (uint64_t)team_bytes(slots) * wpw;
     }
-    if (lng ? 5u * slots < 8u * n1 : slots < 2u * n1) return PPERM_EINVAL;
+    if (lng ? 2u * slots < 3u * n1 : slots < 2u * n1) return PPERM_EINVAL;
     if (bytes > (wpw == 1 ? kLdsLimit : kTeamLdsLimit)) return PPERM_EINVAL;
     sh->slots = (uint32_t)slots;
     sh->lds_team_bytes = team_bytes(slots);
@@ -288,6 +293,7 @@ int pperm_create(const pperm_config* cfg, void* d_workspace, size_t bytes, void*
     x->lay = L;
     x->team_lanes = sh.team_lanes;
     x->slots_log2 = log2u(sh.slots);
+    x->slots = sh.slots;
     x->lds_team_bytes = sh.lds_team_bytes;
     x->lds_wg_bytes = sh.lds_wg_bytes;
     x->long_walk = sh.long_walk;
@@ -331,6 +337,7 @@ int pperm_create(const pperm_config* cfg, void* d_workspace, size_t bytes, void*
     d.row = L.row;
     d.mode = cfg->mode;
     d.slots_log2 = x->slots_log2;
+    d.slots = x->slots;
     d.lds_team_bytes = sh.lds_team_bytes;
     d.key0 = (uint32_t)cfg->seed;
     d.key1 = (uint32_t)(cfg->seed >> 32) ^ cfg->stream_id;
@@ -1375,7 +1382,7 @@ int pperm_launch_shape(const pperm_ctx* x, uint32_t* walks_per_wave, uint32_t* h
                        uint32_t* workgroups) {
     if (!x) return PPERM_EINVAL;
     if (walks_per_wave) *walks_per_wave = 64u / x->team_lanes;
-    if (hash_slots) *hash_slots = 1u << x->slots_log2;
+    if (hash_slots) *hash_slots = x->slots;
     if (workgroups) *workgroups = x->workgroups;
     return PPERM_OK;
 }

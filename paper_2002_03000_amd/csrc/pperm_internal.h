@@ -93,7 +93,7 @@ struct ProblemDesc {
     uint32_t step_cap;    // the configuration's step cap per sequence and call (0: default)
     SumRec* LR;           // [N][row] per-sequence sums of W * R^2, or nullptr
     uint32_t ckey;        // 1: cubic walks with 32-bit keys (n_max <= COMPACT3_MAX_N)
-    uint32_t pad2;
+    uint32_t slots;       // occupancy-table slots of one walk (wave per walk)
 };
 
 // One problem's share of a launch: its tours, its step cap, and the index of

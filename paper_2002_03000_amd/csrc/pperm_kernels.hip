@@ -759,7 +759,7 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
     // sequence's own per-length sums (moved in at the start of the sequence's
     // tours and back out at their end)
     Key* table = reinterpret_cast<Key*>(lds);
-    uint16_t* sid = reinterpret_cast<uint16_t*>(lds + (sizeof(Key) << P.slots_log2));
+    uint16_t* sid = reinterpret_cast<uint16_t*>(lds + sizeof(Key) * P.slots);
     const uint32_t row_lds = LONG ? 0u : P.row * (uint32_t)sizeof(SumRec);
     SumRec* Ls = LONG ? P.L + (size_t)s * P.row : reinterpret_cast<SumRec*>(lds + P.lds_team_bytes);
     // (observables) the sequence's per-length sums of W * R^2, after its sums
@@ -775,9 +775,12 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
         else *p = v;
     };
     const int lane = (int)threadIdx.x;
-    const uint32_t S = 1u << P.slots_log2;
-    const uint32_t smask = S - 1u;
-    const uint32_t hshift = 32u - P.slots_log2;
+    // S slots, a power of two or 1.5 times one: the home slot of a key is the
+    // high word of hash * S (for S = 2^b the top b bits of the hash), and a
+    // probe position past the end wraps by one subtraction (min(x, x - S) on
+    // unsigned values: positions stay below 2S)
+    const uint32_t S = P.slots;
+    auto wrap = [S](uint32_t x) { return __builtin_elementwise_min(x, x - S); };
 
     // probe-lane role: direction-major, W lanes per direction (lanes past the
     // 2d directions read a slot that no mask ever selects)
@@ -806,7 +809,7 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
     for (uint32_t i = (uint32_t)lane; i < S; i += 64) table[i] = (Key)0;
     wave_fence();
     const Key origin_key = L_::origin();
-    const uint32_t origin_slot = L_::hash(origin_key) >> hshift;
+    const uint32_t origin_slot = __umulhi(L_::hash(origin_key), S);
     if (lane == 0) {
         table[origin_slot] = origin_key;
         sid[0] = (uint16_t)origin_slot;
@@ -915,8 +918,8 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
             // empty slot, so a direction is occupied iff a window shows the key
             // and free iff it shows an empty slot and no key.
             const Key nk = L_::next(ekey, pdelta);
-            const uint32_t home = L_::hash(nk) >> hshift;
-            uint32_t slot = (home + (uint32_t)poff) & smask;
+            const uint32_t home = __umulhi(L_::hash(nk), S);
+            uint32_t slot = wrap(home + (uint32_t)poff);
             Key v = table[slot];
             const SumRec nxt = rec_ld(Ls + (n + 1 + vz));
             SumRec nxr = {0.0, 0, 0u};
@@ -962,7 +965,7 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
                 while (pending != 0u) {
                     // a run longer than the window: read the next W positions
                     base += W;
-                    slot = (home + base) & smask;
+                    slot = wrap(home + base);
                     v = table[slot];
                     const uint64_t act = fields_lanes<D>(pending);
                     const uint64_t hd2 = fields_any<D>(__ballot(v == nk) & act);

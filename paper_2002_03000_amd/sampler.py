@@ -441,7 +441,7 @@ def pool_script(pool_bytes, ops):
 
 
 def autotune(dim, n_max, n_sequences, mode="shared", trial=(1, 1, 2, 4, 8), seed=0x5EED,
-             walks_per_wave=(1, 2, 4, 8), slot_factors=(1, 2), device=None, untimed=0):
+             walks_per_wave=(1, 2, 4, 8), slot_factors=(0.75, 1, 1.5, 2), device=None, untimed=0):
     """Choose the launch shape (walks per wave, hash slots, and for one walk
     per wave whether the per-length sums stay in global memory) for a
     configuration by timing a short trial schedule of every candidate on a
@@ -457,7 +457,9 @@ def autotune(dim, n_max, n_sequences, mode="shared", trial=(1, 1, 2, 4, 8), seed
         s0 *= 2
     table = []
     warmed = False
-    shapes = [(wpw, s0 * f, sg) for wpw in walks_per_wave for f in slot_factors
+    # (3 * 2^k slots exist for one walk per wave only; shapes that do not fit
+    # the configuration are refused by the library and skipped)
+    shapes = [(wpw, int(s0 * f), sg) for wpw in walks_per_wave for f in slot_factors
               for sg in ((False, True) if wpw == 1 else (False,))]
     for wpw, slots, sg in shapes:
         def make():

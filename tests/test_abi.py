@@ -49,10 +49,22 @@ def _ws(cfg):
     return rc, n.value
 
 
+@pytest.mark.parametrize("kw", [dict(hash_slots=384, n_max=100), dict(hash_slots=1536, n_max=700),
+                                dict(hash_slots=1536, n_max=1000, dim=3, flags=4), dict(hash_slots=96, n_max=40),
+                                dict(hash_slots=3072, n_max=1500, dim=3)])
+def test_one_and_a_half_times_a_power_of_two_slots(kw):
+    # one walk per wave may use 3 * 2^k slots: at most half full with the sums
+    # in LDS, at most 2/3 with the sums in global memory
+    rc, _ = _ws(_cfg(**kw))
+    assert rc == 0
+
+
 @pytest.mark.parametrize("bad", [dict(dim=1), dict(dim=4), dict(n_max=0), dict(n_max=32767),
                                  dict(n_sequences=0), dict(mode=3), dict(flags=8), dict(flags=4, walks_per_wave=4),
                                  dict(flags=2, mode=1), dict(flags=2, walks_per_wave=2),
                                  dict(hash_slots=100), dict(hash_slots=128, n_max=100),
+                                 dict(hash_slots=320), dict(hash_slots=384, n_max=200),
+                                 dict(hash_slots=768, walks_per_wave=2), dict(hash_slots=48),
                                  dict(walks_per_wave=3), dict(walks_per_wave=32),
                                  dict(dim=3, walks_per_wave=16)])
 def test_invalid_configurations_are_rejected(bad):
@@ -128,10 +140,10 @@ def test_server_pool_allocator_first_fit_and_coalescing(seed):
 
 
 @pytest.mark.parametrize("dim,n_max,ok", [(2, 5000, True), (2, 10000, True), (2, 16383, True), (2, 16384, False),
-                                          (3, 10000, True), (3, 10239, True), (3, 10240, False)])
+                                          (3, 10000, True), (3, 10921, True), (3, 10922, False)])
 def test_long_walk_limits(dim, n_max, ok):
     # walks whose per-length sums no longer fit in LDS beside the occupancy
-    # table keep them in global memory; the table (up to 5/8 full) and the
+    # table keep them in global memory; the table (up to 2/3 full) and the
     # slot ids must still fit in one workgroup's 160 KiB of LDS
     rc, n = _ws(_cfg(dim=dim, n_max=n_max, n_sequences=256))
     assert (rc == 0) == ok

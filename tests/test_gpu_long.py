@@ -178,3 +178,43 @@ def test_global_sums_walker_independent_and_rosenbluth_batched():
         fin = np.isfinite(olc)
         assert np.array_equal(fin, np.isfinite(lc))
         np.testing.assert_allclose(lc[fin], olc[fin], rtol=1e-12, atol=0)
+
+
+def test_one_and_a_half_power_of_two_tables_change_no_bit():
+    # occupancy tables of 3 * 2^k slots (hash by the high word of hash * S,
+    # probe positions wrapped by one subtraction), with the sums in LDS and in
+    # global memory, batched and chained: the oracle's bits and the default
+    # shape's
+    from paper_2002_03000_amd import Batch, ParallelFlatPERM, run_job
+    specs = [(2, 150, 30, 41, 384, False), (3, 300, 50, 42, 768, False),
+             (2, 700, 40, 43, 1536, False), (3, 1000, 64, 44, 1536, True)]
+    sched = [1, 1, 2, 4]
+    mk = lambda slots: [ParallelFlatPERM(d, n, N, sd, stream_id=i, hash_slots=(hs if slots else 0), sums_global=sg)
+                        for i, (d, n, N, sd, hs, sg) in enumerate(specs)]
+    batched, default, chained = mk(True), mk(False), mk(True)
+    for g, (d, n, N, sd, hs, sg) in zip(batched, specs):
+        assert g.launch_shape()["hash_slots"] == hs
+    b = Batch(len(specs))
+    for T in sched:
+        b.run_tours(batched, [T] * len(specs))
+        for g in batched:
+            g.merge_epoch()
+        for g in default:
+            g.run_tours(T)
+            g.merge_epoch()
+    run_job(chained, [sched] * len(specs))
+    for i, (x, y, z) in enumerate(zip(batched, default, chained)):
+        lx, hx, mx = x.estimates()
+        for other, label in ((y, "default shape"), (z, "chained")):
+            lo, ho, mo = other.estimates()
+            assert mx == mo and np.array_equal(hx, ho), f"problem {i} vs {label}"
+            assert np.array_equal(lx.view(np.uint64), lo.view(np.uint64)), f"problem {i} vs {label}"
+            a_, b_ = x.sequence_stats(), other.sequence_stats()
+            assert all(np.array_equal(a_[f], b_[f]) for f in a_.dtype.names), f"problem {i} vs {label}: stats"
+        d, n, N, sd, hs, sg = specs[i]
+        o = oracle.Oracle(d, n, N, sd, stream=i)
+        for T in sched:
+            assert not o.run_tours(T)
+            o.merge_epoch()
+        assert_pooled_equal(x, o, f"{hs}-slot table, problem {i}")
+        print(f"problem {i}: {hs} slots, d={d}, n_max={n}: identical", flush=True)
