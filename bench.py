@@ -193,6 +193,10 @@ def main():
     ap.add_argument("--serve-max-sequences", type=int, default=262144)
     ap.add_argument("--plain-full", action="store_true",
                     help="batched / served: time the plain path on every problem, not a stratified subset")
+    ap.add_argument("--accuracy-runs", type=int, default=None,
+                    help="independent runs for the c_n accuracy report (default 8; long2d 0; 0: none)")
+    ap.add_argument("--reference-factor", type=int, default=16,
+                    help="accuracy report: the reference run has this many times the steady tours")
     ap.add_argument("--plain-strata", type=int, default=32,
                     help="batched / served: strata (by walk-steps) of the plain-path subset")
     ap.add_argument("--no-probe", action="store_true", help="skip the VALU / LDS / L2 ceiling probes")
@@ -226,6 +230,8 @@ def main():
               "of the method is described in the design notes, not run.", file=sys.stderr)
         sys.exit(2)
 
+    if args.accuracy_runs is None:
+        args.accuracy_runs = 0 if args.workload == "long2d" else 8
     if args.workload == "batched":
         run_batched(args)
         return
@@ -348,6 +354,8 @@ def main():
         line["gamma_nmin"] = gamma_extrapolation(results[0][0], p.n_max)
     if not args.no_latency_bound:
         line["latency_bound"] = latency_bound(p, make, sched, elapsed / args.steps, args.sums_global)
+    if args.accuracy_runs > 1 and not args.epochs:
+        line["accuracy"] = accuracy(p, make, job, results, args.accuracy_runs, args.reference_factor)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(p)
     print(json.dumps(line), flush=True)
@@ -369,6 +377,43 @@ def gamma_extrapolation(log_c, n_max):
     free = analysis.gamma_nmin_extrapolation(log_c, n_mins, n_max=n_max)
     fixed = analysis.gamma_nmin_extrapolation(log_c, n_mins, n_max=n_max, log_mu=0.970081147258)
     return {"three_parameter": free, "two_parameter_mu_fixed": fixed}
+
+
+def accuracy(p, make, job, results, runs, factor):
+    """The c_n relative error at this fixed budget: ĉ_{n_max} over `runs`
+    independent runs of the job (the timed ones and more with the next seeds),
+    their relative standard deviation, their bias against a reference run of
+    the same configuration with `factor` times the steady-state tours, and
+    T_M of eqn (9) over n <= n_max against that reference, per run.  Outside
+    the timed region."""
+    import numpy as np
+    from paper_2002_03000_amd import analysis
+    logs = [r[0] for r in results]
+    for i in range(len(results), runs):
+        g = make(p.seed + i)
+        logs.append(job(g)[0])
+        g.close()
+    head = p.schedule()[:len(p.schedule()) - p.epochs + 1]
+    ref_sched = head + [p.tours_per_epoch] * ((p.epochs - 1) * factor)
+    g = make(p.seed + 5000)
+    t0 = time.perf_counter()
+    for k, T in enumerate(ref_sched):
+        g.run_tours(T)
+        g.merge_epoch()
+        if k % 50 == 49:
+            g.sync()
+            _log(f"accuracy: reference epoch {k + 1}/{len(ref_sched)}, {time.perf_counter() - t0:.0f} s")
+    ref, _, ref_tours = g.estimates()
+    g.close()
+    top = np.array([lc[p.n_max] for lc in logs])
+    ratio = np.exp(top - ref[p.n_max])                     # ĉ / ĉ_ref at n_max
+    tm = [analysis.total_abs_error(ref, lc, M=p.n_max) for lc in logs]
+    return {"runs": len(logs), "reference_tours": int(ref_tours), "job_tours": int(p.total_tours),
+            "c_nmax_rel_std": float(np.std(ratio, ddof=1) / np.mean(ratio)),
+            "c_nmax_bias_vs_reference": float(np.mean(ratio) - 1.0),
+            "c_nmax_bias_se": float(np.std(ratio, ddof=1) / np.sqrt(len(ratio))),
+            "T_M_mean": float(np.mean(tm)), "T_M_max": float(np.max(tm)),
+            "reference_log_c_nmax": float(ref[p.n_max])}
 
 
 def latency_bound(p, make, sched, seconds_per_job, sums_global=False):
