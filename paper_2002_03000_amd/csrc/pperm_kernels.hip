@@ -1386,7 +1386,9 @@ __device__ void job_merge(const JobArgs& A, const JobProblem& J, const ProblemDe
     }
 }
 
-__global__ void __launch_bounds__(64) job_kernel(JobArgs A) {
+// (at most 128 VGPRs: four waves per SIMD; the register pressure this adds
+// costs two spills in a chained item's merge part, none in the step loop)
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) job_kernel(JobArgs A) {
     extern __shared__ __align__(16) unsigned char lds[];
     const int lane = (int)threadIdx.x;
     uint64_t idle_since = __builtin_amdgcn_s_memrealtime();
