@@ -40,8 +40,10 @@ def lds_bytes_per_step(dim, n_max):
     key = 4 if (dim == 2 or n_max <= 1023) else 8
     return 2 * dim * key
 # Algorithmic L2 bytes per walk-step: the pooled sum of the length read (8),
-# the sequence's sum read and written (16) and its count read and written (8).
-L2_BYTES_PER_STEP = 32
+# and where the sequence's sums live in global memory also its sum read and
+# written (16) and its count read and written (8).
+def l2_bytes_per_step(sums_global):
+    return 32 if sums_global else 8
 # MI355X 32-bit VALU peak: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz = 78.6 T lane-op/s, the
 # published FP32 vector rate (157.3 TFLOP/s) with one operation per FMA.  (FP64 operations,
 # most of the prune/enrich arithmetic, issue at half that rate.)
@@ -146,14 +148,14 @@ def cpu_baseline(p, budget_s=4.0, runs=3):
             "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
 
 
-def probed_roofline(dim, n_max, steps_per_s, ops_per_step, probes):
+def probed_roofline(steps_per_s, ops_per_step, lds_per_step, l2_per_step, probes):
     """Achieved fractions of the probed VALU, LDS and L2 ceilings at the growth
     kernel's walk-step rate (algorithmic work per step)."""
     out = {}
     for name, per_step, peak, unit in (
             ("valu", ops_per_step, probes["valu_lane_ops_per_s"], "lane-op/s"),
-            ("lds", lds_bytes_per_step(dim, n_max), probes["lds_bytes_per_s"], "B/s"),
-            ("l2", L2_BYTES_PER_STEP, probes["l2_bytes_per_s"], "B/s")):
+            ("lds", lds_per_step, probes["lds_bytes_per_s"], "B/s"),
+            ("l2", l2_per_step, probes["l2_bytes_per_s"], "B/s")):
         ach = steps_per_s * per_step
         out[name] = {"achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak, "per_step": per_step}
     out["binding_of_three"] = max(("valu", "lds", "l2"), key=lambda k: out[k]["frac"])
@@ -346,7 +348,9 @@ def main():
                      if not args.epochs else None,
                      "kernel": kernel, "avg_launch_ms": run_ms / launches,
                      "alg_ops_per_step": ops,
-                     "probed": probed_roofline(p.dim, p.n_max, kernel_rate, ops, probes) if probes else None},
+                     "probed": probed_roofline(kernel_rate, ops, lds_bytes_per_step(p.dim, p.n_max),
+                                               l2_bytes_per_step(args.sums_global or args.workload == "long2d"),
+                                               probes) if probes else None},
         "probes": probes,
         "cpu_baseline": None,
     }
@@ -606,6 +610,11 @@ def run_batched(args):
     value = steps_total / elapsed_total
     ops = (ALG_OPS_PER_STEP[2] * by_dim[2] + ALG_OPS_PER_STEP[3] * by_dim[3]) / max(1, sum(by_dim.values()))
     achieved = steps_total / (run_ms / 1e3) * ops / 1e12
+    # algorithmic LDS and L2 bytes per step, weighted by each problem's steps
+    # (the mix's sums stay in LDS: n_max <= 2048)
+    w_steps = max(1, sum(per))
+    lds_avg = sum(int(st) * lds_bytes_per_step(p.dim, p.n_max) for p, st in zip(mix, per)) / w_steps
+    probes = None if args.no_probe else probe_ceilings()
 
     # the plain path on the same problems and seeds (those of the first timed
     # job), one problem at a time through pperm_run_tours / pperm_merge_epoch
@@ -654,7 +663,10 @@ def run_batched(args):
                      "frac": achieved / ALU_PEAK_TOPS, "traffic": None,
                      "kernel": "batch_kernel" if args.lockstep else "job_kernel",
                      "avg_launch_ms": run_ms / len(events),
-                     "alg_ops_per_step": ops},
+                     "alg_ops_per_step": ops,
+                     "probed": probed_roofline(steps_total / (run_ms / 1e3), ops, lds_avg, l2_bytes_per_step(False),
+                                               probes) if probes else None},
+        "probes": probes,
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:
@@ -775,8 +787,12 @@ def run_served(args):
     _log(f"plain path: {plain['timed_problems']} jobs timed in {plain['timed_seconds']:.1f} s, "
          f"{plain['value']:.3e} walk-steps/s")
 
-    ops = (ALG_OPS_PER_STEP[2] + ALG_OPS_PER_STEP[3]) / 2
+    # algorithmic work per step, weighted by each job's steps
+    w_steps = max(1, sum(job_steps))
+    ops = sum(st * ALG_OPS_PER_STEP[j.problem.dim] for j, st in zip(jobs, job_steps)) / w_steps
+    lds_avg = sum(st * lds_bytes_per_step(j.problem.dim, j.problem.n_max) for j, st in zip(jobs, job_steps)) / w_steps
     achieved = steps_done / (gpu_ms / 1e3) * ops / 1e12
+    probes = None if args.no_probe else probe_ceilings()
     line = {
         "metric": METRIC,
         "value": value,
@@ -806,7 +822,10 @@ def run_served(args):
         "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
                      "frac": achieved / ALU_PEAK_TOPS, "traffic": None,
                      "kernel": "server step (job_kernel, time-sliced)", "avg_launch_ms": gpu_ms / max(1, n_steps),
-                     "alg_ops_per_step": ops},
+                     "alg_ops_per_step": ops,
+                     "probed": probed_roofline(steps_done / (gpu_ms / 1e3), ops, lds_avg, l2_bytes_per_step(False),
+                                               probes) if probes else None},
+        "probes": probes,
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:
