@@ -94,7 +94,7 @@ struct Shape {
 // The occupancy table holds at most n_max + 1 sites; at least twice that many
 // slots keeps linear-probing runs short.  One walk per wavefront keeps the
 // sequence's per-length sums (and, with observables, its sums of W * R^2) in
-// LDS beside the table and the bottom of its copy stack.  Where that does not
+// LDS beside the table.  Where that does not
 // fit (walks of several thousand steps), or where PPERM_FLAG_SUMS_GLOBAL asks
 // for more walks per compute unit, the sums stay in global memory and
 // the table may fill up to 2/3 (at least 1.5 (n_max + 1) slots) so that table

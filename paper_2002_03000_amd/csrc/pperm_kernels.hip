@@ -15,10 +15,11 @@
 //   - the random numbers: lane i computes the Philox4x32-10 block of event
 //     k0+i, so one pass of the (quarter-rate) multiplies serves 64 events;
 //   - the LIFO deletion of abandoned sites after a backtrack.
-// The walk's occupancy table (packed int16 coordinates, linear probing,
-// restored exactly by LIFO deletion through remembered slot ids), the slot
-// ids, the sequence's own per-length sums and the bottom of its copy stack
-// live in LDS; the pooled sums are read with scalar loads.  A second kernel
+// The walk's occupancy table (packed coordinates, linear probing, restored
+// exactly by LIFO deletion through remembered slot ids), the slot ids and the
+// sequence's own per-length sums live in LDS (the sums in global memory for
+// long walks); the 64 most recent pending copies live in the lanes of a few
+// vector registers; the pooled sums are read with scalar loads.  A second kernel
 // (run_kernel) packs 64/TS walks into a wave as teams of TS lanes.
 //
 // Determinism.  Every floating-point decision uses the same IEEE operations
