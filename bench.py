@@ -271,6 +271,14 @@ def main():
 
     sched = p.schedule()
 
+    last_note = [time.perf_counter()]
+
+    def note(msg):
+        # a progress line at most every 20 s (long jobs: one epoch can take seconds)
+        if time.perf_counter() - last_note[0] > 20:
+            last_note[0] = time.perf_counter()
+            _log(msg)
+
     def job(g, ev=None):
         for T in sched:
             if ev is not None:
@@ -282,7 +290,9 @@ def main():
             else:
                 g.run_tours(T)
             g.merge_epoch()
-        return g.estimates()
+        out = g.estimates()
+        note(f"{args.workload}: a job done")
+        return out
 
     # warmup (its own seeds)
     for i in range(args.warmup):
@@ -434,12 +444,16 @@ def latency_bound(p, make, sched, seconds_per_job, sums_global=False):
     g = make(p.seed)
     prev = np.zeros(p.n_sequences, dtype=np.uint64)
     crit = 0
-    for T in sched:
+    t_note = time.perf_counter()
+    for e, T in enumerate(sched):
         g.run_tours(T)
         g.merge_epoch()
         st = g.sequence_stats()["steps"]
         crit += int((st - prev).max())
         prev = st
+        if time.perf_counter() - t_note > 20:
+            t_note = time.perf_counter()
+            _log(f"latency bound: replay epoch {e + 1}/{len(sched)}")
     g.close()
     # one wave alone: a single sequence through the same schedule (the first
     # epochs warm its own estimates), timed over the full-length epochs
@@ -448,12 +462,22 @@ def latency_bound(p, make, sched, seconds_per_job, sums_global=False):
     for T in sched[:head]:
         lone.run_tours(T)
         lone.merge_epoch()
+        lone.sync()
+        if time.perf_counter() - t_note > 20:
+            t_note = time.perf_counter()
+            _log("latency bound: one sequence alone, warm-up epochs")
     torch.cuda.synchronize()
     s0 = lone.stats()["steps"]
     t0 = time.perf_counter()
-    for T in sched[head:head + 8]:
+    for k, T in enumerate(sched[head:head + 8]):
         lone.run_tours(T)
         lone.merge_epoch()
+        # (a wait per epoch, tens of microseconds against epochs of milliseconds
+        # or more, so that a long run can say how far it is)
+        lone.sync()
+        if time.perf_counter() - t_note > 20:
+            t_note = time.perf_counter()
+            _log(f"latency bound: one sequence alone, timed epoch {k + 1}/8")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     lone_steps = lone.stats()["steps"] - s0
