@@ -462,7 +462,7 @@ def latency_bound(p, make, sched, seconds_per_job, sums_global=False):
     for T in sched[:head]:
         lone.run_tours(T)
         lone.merge_epoch()
-        lone.sync()
+        torch.cuda.synchronize()
         if time.perf_counter() - t_note > 20:
             t_note = time.perf_counter()
             _log("latency bound: one sequence alone, warm-up epochs")
@@ -473,8 +473,10 @@ def latency_bound(p, make, sched, seconds_per_job, sums_global=False):
         lone.run_tours(T)
         lone.merge_epoch()
         # (a wait per epoch, tens of microseconds against epochs of milliseconds
-        # or more, so that a long run can say how far it is)
-        lone.sync()
+        # or more, so that a long run can say how far it is; a stream wait, not
+        # pperm_sync: a lone long walk may stop on its step cap, and its steps up
+        # to there still time the step)
+        torch.cuda.synchronize()
         if time.perf_counter() - t_note > 20:
             t_note = time.perf_counter()
             _log(f"latency bound: one sequence alone, timed epoch {k + 1}/8")
