@@ -57,9 +57,9 @@ PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2002_03000_amd", "csrc", "pperm_kernels.hip")
 
 
-def measured_traffic(name):
-    """HBM bytes per launch of the growth kernel from a committed counter
-    summary, or None when the kernel source has changed since it was taken."""
+def profile_field(name, field):
+    """One figure of a committed counter summary, or None when the summary is
+    missing or the kernel source has changed since it was taken."""
     path = os.path.join(PROFILES, name)
     if not os.path.exists(path):
         return None
@@ -68,9 +68,33 @@ def measured_traffic(name):
         if ":" in line and not line.startswith(("|", "#", " ")):
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
-    if fields.get("kernel_code_sha256") != kernel_code_digest() or "traffic_bytes_per_launch" not in fields:
+    if fields.get("kernel_code_sha256") != kernel_code_digest() or field not in fields:
         return None
-    return int(fields["traffic_bytes_per_launch"])
+    return fields[field]
+
+
+def measured_traffic(name):
+    """HBM bytes per launch of the growth kernel (FETCH_SIZE + WRITE_SIZE,
+    calibrated), from a committed counter summary of the current kernel."""
+    v = profile_field(name, "traffic_bytes_per_launch")
+    return None if v is None else int(v)
+
+
+def issue_fraction(steps_per_s, kernel, workload, probes):
+    """The kernel's instruction issue against the SIMD issue ceilings the
+    probes measure: instructions per walk-step (the SQ_INSTS counters of a
+    committed summary of the current kernel) times the walk-step rate, against
+    the mixed vector/scalar stream's rate and the scalar-only rate."""
+    v = profile_field(f"{kernel}_{workload}_sq_counters.md", "instructions_per_step")
+    if v is None or not probes:
+        return None
+    per_step = float(v)
+    ach = steps_per_s * per_step
+    hz = probes["simds"] * probes["clock_khz"] * 1e3
+    return {"instructions_per_step": per_step, "achieved": ach, "unit": "wave-instr/s",
+            "peak_mixed": probes["mixed_instr_per_s"], "frac_mixed": ach / probes["mixed_instr_per_s"],
+            "peak_scalar_only": probes["salu_instr_per_s"],
+            "per_simd_cycle": ach / hz, "peak_mixed_per_simd_cycle": probes["mixed_instr_per_s"] / hz}
 
 
 def kernel_code_digest():
@@ -360,7 +384,8 @@ def main():
                      "alg_ops_per_step": ops,
                      "probed": probed_roofline(kernel_rate, ops, lds_bytes_per_step(p.dim, p.n_max),
                                                l2_bytes_per_step(args.sums_global or args.workload == "long2d"),
-                                               probes) if probes else None},
+                                               probes) if probes else None,
+                     "issue": issue_fraction(kernel_rate, kernel, args.workload, probes)},
         "probes": probes,
         "cpu_baseline": None,
     }

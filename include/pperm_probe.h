@@ -5,8 +5,11 @@
  * The method's hot path is no dense contraction and no stream: its steps
  * issue 32-bit vector ALU work, read and write the per-walk tables in LDS, and
  * read the pooled sums through L2.  The rooflines it is reported against are
- * measured on the device itself by the three microbenchmarks of this call, not
- * taken from a data sheet.
+ * measured on the device itself by the microbenchmarks of this call, not
+ * taken from a data sheet.  Beside the three resources, two probes measure
+ * how many instructions a SIMD issues when every wave's stream is scalar, or
+ * alternates vector and scalar instructions as a walk-step's stream does
+ * (about half of each).
  */
 #ifndef PPERM_PROBE_H
 #define PPERM_PROBE_H
@@ -25,11 +28,20 @@ typedef struct pperm_probe_result {
     double valu_ms, lds_ms, l2_ms; /* duration of each timed launch                            */
     uint32_t compute_units;       /* CUs the launches were sized for                           */
     uint32_t l2_buffer_bytes;     /* size of the L2-resident buffer that was read              */
+    double salu_instr_per_s;      /* wave instructions per second, scalar ALU only, whole device */
+    double mixed_instr_per_s;     /* wave instructions per second, vector and scalar ALU
+                                     alternating in each wave, whole device                    */
+    double salu_ms, mixed_ms;     /* duration of each timed launch                            */
+    uint32_t clock_khz;           /* the device's peak engine clock (HIP attribute), kHz       */
+    uint32_t simds;               /* SIMDs the issue rates are spread over (4 per CU)          */
 } pperm_probe_result;
 
-/* Run the three probes on the current device, in order, on hip_stream (NULL:
- * the default stream), each once untimed and once timed with HIP events, and
- * synchronise.  d_buffer: caller-owned scratch device memory of at least 1 MiB
+/* Run the probes on the current device, in order (VALU, LDS, L2, scalar issue,
+ * mixed issue), on hip_stream (NULL: the default stream), each once untimed
+ * and once timed with HIP events, and synchronise.  Every issue probe runs
+ * eight waves per SIMD, each with independent dependency chains, and counts
+ * the instructions of its unrolled body only (loop control excluded, so the
+ * rates are slight underestimates).  d_buffer: caller-owned scratch device memory of at least 1 MiB
  * (PPERM_PROBE_BUFFER_BYTES), 256-byte aligned, whose contents do not matter:
  * the L2 probe reads its first MiB, and each probe keeps its work live with a
  * store into the first 256 bytes that happens only when a checksum of what it

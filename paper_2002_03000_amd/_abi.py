@@ -69,7 +69,10 @@ class JobReport(ctypes.Structure):
 class ProbeResult(ctypes.Structure):
     _fields_ = [("valu_lane_ops_per_s", ctypes.c_double), ("lds_bytes_per_s", ctypes.c_double),
                 ("l2_bytes_per_s", ctypes.c_double), ("valu_ms", ctypes.c_double), ("lds_ms", ctypes.c_double),
-                ("l2_ms", ctypes.c_double), ("compute_units", ctypes.c_uint32), ("l2_buffer_bytes", ctypes.c_uint32)]
+                ("l2_ms", ctypes.c_double), ("compute_units", ctypes.c_uint32), ("l2_buffer_bytes", ctypes.c_uint32),
+                ("salu_instr_per_s", ctypes.c_double), ("mixed_instr_per_s", ctypes.c_double),
+                ("salu_ms", ctypes.c_double), ("mixed_ms", ctypes.c_double), ("clock_khz", ctypes.c_uint32),
+                ("simds", ctypes.c_uint32)]
 
 
 PROBE_BUFFER_BYTES = 1 << 20

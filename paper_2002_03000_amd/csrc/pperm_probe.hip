@@ -1,6 +1,7 @@
-// Microbenchmarks of the three ceilings the growth kernel is reported against
+// Microbenchmarks of the ceilings the growth kernel is reported against
 // (include/pperm_probe.h): 32-bit VALU issue, LDS read bandwidth and L2 read
-// bandwidth, each measured on the whole device with HIP events.
+// bandwidth, and the instruction issue rate of a SIMD for a scalar-only and a
+// mixed vector/scalar stream, each measured on the whole device with HIP events.
 //
 // Every probe fills the device (workgroups per CU sized for its resource) and
 // keeps its result live with a store that never happens in practice (the
@@ -23,6 +24,9 @@ constexpr uint32_t kLdsBlocksPerCU = 2;      // 2 x 64 KiB of the 160 KiB
 constexpr uint32_t kL2Bytes = 1u << 20;      // read by every workgroup, resident in each XCD's L2
 constexpr uint32_t kL2Passes = 4;
 constexpr uint32_t kL2BlocksPerCU = 4;
+constexpr uint32_t kIssueIters = 8192;
+constexpr uint32_t kIssuePerIter = 32;       // instructions of one unrolled body
+constexpr uint32_t kIssueBlocksPerCU = 8;    // 8 waves per SIMD
 static_assert(kL2Bytes <= PPERM_PROBE_BUFFER_BYTES, "the L2 probe reads the caller's buffer");
 
 __global__ void __launch_bounds__(256) valu_probe_kernel(uint32_t* sink, uint32_t k) {
@@ -92,6 +96,54 @@ __global__ void __launch_bounds__(256) l2_probe_kernel(const uint4* buf, uint32_
     if ((acc0 ^ acc1) == 0x9E3779B9u) sink[threadIdx.x & 63u] = acc0;
 }
 
+// Scalar ALU only: eight independent chains of 32-bit adds and xors on
+// wave-uniform values (each wave has its own scalar registers).
+__global__ void __launch_bounds__(256) salu_probe_kernel(uint32_t* sink, uint32_t k) {
+    uint32_t b0 = blockIdx.x, b1 = b0 + 1u, b2 = b0 + 2u, b3 = b0 + 3u;
+    uint32_t b4 = b0 + 4u, b5 = b0 + 5u, b6 = b0 + 6u, b7 = b0 + 7u;
+    for (uint32_t i = 0; i < kIssueIters; ++i) {
+        asm volatile(
+            "s_add_u32 %0, %0, %8\n\ts_add_u32 %1, %1, %8\n\ts_add_u32 %2, %2, %8\n\ts_add_u32 %3, %3, %8\n\t"
+            "s_add_u32 %4, %4, %8\n\ts_add_u32 %5, %5, %8\n\ts_add_u32 %6, %6, %8\n\ts_add_u32 %7, %7, %8\n\t"
+            "s_xor_b32 %0, %0, %8\n\ts_xor_b32 %1, %1, %8\n\ts_xor_b32 %2, %2, %8\n\ts_xor_b32 %3, %3, %8\n\t"
+            "s_xor_b32 %4, %4, %8\n\ts_xor_b32 %5, %5, %8\n\ts_xor_b32 %6, %6, %8\n\ts_xor_b32 %7, %7, %8\n\t"
+            "s_add_u32 %0, %0, %8\n\ts_add_u32 %1, %1, %8\n\ts_add_u32 %2, %2, %8\n\ts_add_u32 %3, %3, %8\n\t"
+            "s_add_u32 %4, %4, %8\n\ts_add_u32 %5, %5, %8\n\ts_add_u32 %6, %6, %8\n\ts_add_u32 %7, %7, %8\n\t"
+            "s_xor_b32 %0, %0, %8\n\ts_xor_b32 %1, %1, %8\n\ts_xor_b32 %2, %2, %8\n\ts_xor_b32 %3, %3, %8\n\t"
+            "s_xor_b32 %4, %4, %8\n\ts_xor_b32 %5, %5, %8\n\ts_xor_b32 %6, %6, %8\n\ts_xor_b32 %7, %7, %8"
+            : "+s"(b0), "+s"(b1), "+s"(b2), "+s"(b3), "+s"(b4), "+s"(b5), "+s"(b6), "+s"(b7)
+            : "s"(k)
+            : "scc");
+    }
+    const uint32_t x = b0 ^ b1 ^ b2 ^ b3 ^ b4 ^ b5 ^ b6 ^ b7;
+    if (x == 0x9E3779B9u) sink[threadIdx.x & 63u] = x;
+}
+
+// Vector and scalar ALU alternating in each wave's stream (16 + 16 per body),
+// four independent chains of each, as a walk-step interleaves its lane work
+// with its wave-uniform control.
+__global__ void __launch_bounds__(256) mixed_probe_kernel(uint32_t* sink, uint32_t k) {
+    uint32_t a0 = threadIdx.x, a1 = a0 + 1u, a2 = a0 + 2u, a3 = a0 + 3u;
+    uint32_t b0 = blockIdx.x, b1 = b0 + 1u, b2 = b0 + 2u, b3 = b0 + 3u;
+    const uint32_t kv = k + threadIdx.x;
+    for (uint32_t i = 0; i < kIssueIters; ++i) {
+        asm volatile(
+            "v_add_u32 %0, %0, %9\n\ts_add_u32 %4, %4, %8\n\tv_add_u32 %1, %1, %9\n\ts_add_u32 %5, %5, %8\n\t"
+            "v_add_u32 %2, %2, %9\n\ts_add_u32 %6, %6, %8\n\tv_add_u32 %3, %3, %9\n\ts_add_u32 %7, %7, %8\n\t"
+            "v_xor_b32 %0, %0, %9\n\ts_xor_b32 %4, %4, %8\n\tv_xor_b32 %1, %1, %9\n\ts_xor_b32 %5, %5, %8\n\t"
+            "v_xor_b32 %2, %2, %9\n\ts_xor_b32 %6, %6, %8\n\tv_xor_b32 %3, %3, %9\n\ts_xor_b32 %7, %7, %8\n\t"
+            "v_add_u32 %0, %0, %9\n\ts_add_u32 %4, %4, %8\n\tv_add_u32 %1, %1, %9\n\ts_add_u32 %5, %5, %8\n\t"
+            "v_add_u32 %2, %2, %9\n\ts_add_u32 %6, %6, %8\n\tv_add_u32 %3, %3, %9\n\ts_add_u32 %7, %7, %8\n\t"
+            "v_xor_b32 %0, %0, %9\n\ts_xor_b32 %4, %4, %8\n\tv_xor_b32 %1, %1, %9\n\ts_xor_b32 %5, %5, %8\n\t"
+            "v_xor_b32 %2, %2, %9\n\ts_xor_b32 %6, %6, %8\n\tv_xor_b32 %3, %3, %9\n\ts_xor_b32 %7, %7, %8"
+            : "+v"(a0), "+v"(a1), "+v"(a2), "+v"(a3), "+s"(b0), "+s"(b1), "+s"(b2), "+s"(b3)
+            : "s"(k), "v"(kv)
+            : "scc");
+    }
+    const uint32_t x = a0 ^ a1 ^ a2 ^ a3 ^ b0 ^ b1 ^ b2 ^ b3;
+    if (x == 0x9E3779B9u) sink[threadIdx.x & 63u] = x;
+}
+
 char g_err[256];
 
 int fail(hipError_t e, const char* what) {
@@ -158,6 +210,23 @@ extern "C" int pperm_probe(void* d_buffer, size_t bytes, void* hip_stream, pperm
     if (rc) return rc;
     out->l2_ms = ms;
     out->l2_bytes_per_s = (double)ncu * kL2BlocksPerCU * (double)kL2Bytes * kL2Passes / (ms * 1e-3);
+    const double issue_waves = (double)ncu * kIssueBlocksPerCU * 4.0;
+    rc = timed(s, [&] {
+        hipLaunchKernelGGL(salu_probe_kernel, dim3(ncu * kIssueBlocksPerCU), dim3(256), 0, s, sink, 3u);
+    }, &ms);
+    if (rc) return rc;
+    out->salu_ms = ms;
+    out->salu_instr_per_s = issue_waves * kIssueIters * kIssuePerIter / (ms * 1e-3);
+    rc = timed(s, [&] {
+        hipLaunchKernelGGL(mixed_probe_kernel, dim3(ncu * kIssueBlocksPerCU), dim3(256), 0, s, sink, 3u);
+    }, &ms);
+    if (rc) return rc;
+    out->mixed_ms = ms;
+    out->mixed_instr_per_s = issue_waves * kIssueIters * kIssuePerIter / (ms * 1e-3);
+    int clk = 0;
+    PROBE_TRY(hipDeviceGetAttribute(&clk, hipDeviceAttributeClockRate, dev));
+    out->clock_khz = (uint32_t)clk;
+    out->simds = 4u * ncu;
     out->compute_units = ncu;
     out->l2_buffer_bytes = kL2Bytes;
     return PPERM_OK;

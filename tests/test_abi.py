@@ -169,3 +169,22 @@ def test_binding_fails_loudly_without_the_library(tmp_path):
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
     assert out.stdout.startswith("raised"), out.stdout + out.stderr
     assert "no CPU fallback" in out.stdout
+
+
+def test_probe_result_fields_match_the_header():
+    src = open(os.path.join(ROOT, "include", "pperm_probe.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    body = re.search(r"typedef struct pperm_probe_result \{(.*?)\} pperm_probe_result;", src, re.S).group(1)
+    names = []
+    for decl in (d.strip() for d in body.split(";")):
+        if decl:
+            names += [n.strip() for n in decl.split(None, 1)[1].split(",")]
+    assert names == [f for f, _ in _abi.ProbeResult._fields_]
+
+
+def test_probe_rejects_bad_buffers_before_any_device_call():
+    lib = _abi.load()
+    res = _abi.ProbeResult()
+    assert lib.pperm_probe(None, 1 << 20, None, ctypes.byref(res)) == -1
+    host = ctypes.create_string_buffer(256)
+    assert lib.pperm_probe(ctypes.cast(host, ctypes.c_void_p), 256, None, ctypes.byref(res)) == -1
