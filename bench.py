@@ -84,7 +84,9 @@ def issue_fraction(steps_per_s, kernel, workload, probes):
     """The kernel's instruction issue against the SIMD issue ceilings the
     probes measure: instructions per walk-step (the SQ_INSTS counters of a
     committed summary of the current kernel) times the walk-step rate, against
-    the mixed vector/scalar stream's rate and the scalar-only rate."""
+    the rates of independent mixed vector/scalar streams, of vector and scalar
+    instructions that feed each other (at eight and at four waves per SIMD),
+    and of scalar-only streams."""
     v = profile_field(f"{kernel}_{workload}_sq_counters.md", "instructions_per_step")
     if v is None or not probes:
         return None
@@ -93,6 +95,9 @@ def issue_fraction(steps_per_s, kernel, workload, probes):
     hz = probes["simds"] * probes["clock_khz"] * 1e3
     return {"instructions_per_step": per_step, "achieved": ach, "unit": "wave-instr/s",
             "peak_mixed": probes["mixed_instr_per_s"], "frac_mixed": ach / probes["mixed_instr_per_s"],
+            "peak_dependent": probes["dependent_instr_per_s"],
+            "frac_dependent": ach / probes["dependent_instr_per_s"],
+            "peak_dependent_4_waves": probes["dependent4_instr_per_s"],
             "peak_scalar_only": probes["salu_instr_per_s"],
             "per_simd_cycle": ach / hz, "peak_mixed_per_simd_cycle": probes["mixed_instr_per_s"] / hz}
 

@@ -9,7 +9,7 @@
  * taken from a data sheet.  Beside the three resources, two probes measure
  * how many instructions a SIMD issues when every wave's stream is scalar, or
  * alternates vector and scalar instructions as a walk-step's stream does
- * (about half of each).
+ * (about half of each), independent of each other or each feeding the next.
  */
 #ifndef PPERM_PROBE_H
 #define PPERM_PROBE_H
@@ -34,20 +34,26 @@ typedef struct pperm_probe_result {
     double salu_ms, mixed_ms;     /* duration of each timed launch                            */
     uint32_t clock_khz;           /* the device's peak engine clock (HIP attribute), kHz       */
     uint32_t simds;               /* SIMDs the issue rates are spread over (4 per CU)          */
+    double dependent_instr_per_s; /* wave instructions per second, vector compares feeding
+                                     scalar mask and count instructions feeding vector adds,
+                                     eight waves per SIMD, whole device                        */
+    double dependent4_instr_per_s; /* the same with four waves per SIMD                        */
+    double dependent_ms, dependent4_ms; /* duration of each timed launch                       */
 } pperm_probe_result;
 
-/* Run the probes on the current device, in order (VALU, LDS, L2, scalar issue,
- * mixed issue), on hip_stream (NULL: the default stream), each once untimed
- * and once timed with HIP events, and synchronise.  Every issue probe runs
- * eight waves per SIMD, each with independent dependency chains, and counts
- * the instructions of its unrolled body only (loop control excluded, so the
- * rates are slight underestimates).  d_buffer: caller-owned scratch device memory of at least 1 MiB
- * (PPERM_PROBE_BUFFER_BYTES), 256-byte aligned, whose contents do not matter:
- * the L2 probe reads its first MiB, and each probe keeps its work live with a
- * store into the first 256 bytes that happens only when a checksum of what it
- * read equals one fixed value.  *out receives the ceilings.  Errors:
- * PPERM_EINVAL (-1) for a null, short or misaligned buffer, PPERM_EDEVICE (-3)
- * for a failed HIP call. */
+/* Run the probes on the current device, in order (VALU, LDS, L2, scalar
+ * issue, mixed issue, dependent issue at eight and at four waves per SIMD), on
+ * hip_stream (NULL: the default stream), each once untimed and once timed with
+ * HIP events, and synchronise.  The issue probes run eight waves per SIMD (the
+ * last one four), each wave with two or more chains, and count the
+ * instructions of their unrolled bodies only (loop control excluded, so the
+ * rates are slight underestimates).  d_buffer: caller-owned scratch device
+ * memory of at least 1 MiB (PPERM_PROBE_BUFFER_BYTES), 256-byte aligned, whose
+ * contents do not matter: the L2 probe reads its first MiB, and each probe
+ * keeps its work live with a store into the first 256 bytes that happens only
+ * when a checksum of what it read equals one fixed value.  *out receives the
+ * ceilings.  Errors: PPERM_EINVAL (-1) for a null, short or misaligned buffer,
+ * PPERM_EDEVICE (-3) for a failed HIP call. */
 #define PPERM_PROBE_BUFFER_BYTES (1u << 20)
 int pperm_probe(void* d_buffer, size_t bytes, void* hip_stream, pperm_probe_result* out);
 

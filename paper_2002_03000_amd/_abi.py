@@ -72,7 +72,9 @@ class ProbeResult(ctypes.Structure):
                 ("l2_ms", ctypes.c_double), ("compute_units", ctypes.c_uint32), ("l2_buffer_bytes", ctypes.c_uint32),
                 ("salu_instr_per_s", ctypes.c_double), ("mixed_instr_per_s", ctypes.c_double),
                 ("salu_ms", ctypes.c_double), ("mixed_ms", ctypes.c_double), ("clock_khz", ctypes.c_uint32),
-                ("simds", ctypes.c_uint32)]
+                ("simds", ctypes.c_uint32), ("dependent_instr_per_s", ctypes.c_double),
+                ("dependent4_instr_per_s", ctypes.c_double), ("dependent_ms", ctypes.c_double),
+                ("dependent4_ms", ctypes.c_double)]
 
 
 PROBE_BUFFER_BYTES = 1 << 20

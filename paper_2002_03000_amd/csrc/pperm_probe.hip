@@ -144,6 +144,34 @@ __global__ void __launch_bounds__(256) mixed_probe_kernel(uint32_t* sink, uint32
     if (x == 0x9E3779B9u) sink[threadIdx.x & 63u] = x;
 }
 
+// Vector and scalar instructions that feed each other, as in a walk-step's
+// neighbour scan: a vector compare writes a lane mask, the scalar unit masks
+// and counts it, and the count feeds the next vector add (two such chains
+// per wave, 16 vector + 16 scalar instructions per body).
+__global__ void __launch_bounds__(256) dependent_probe_kernel(uint32_t* sink, uint32_t k) {
+    uint32_t v0 = threadIdx.x, v1 = threadIdx.x ^ 17u;
+    uint32_t s0 = blockIdx.x + k, s1 = blockIdx.x + 2u * k;
+    uint64_t m0 = 0, m1 = 0;
+    for (uint32_t i = 0; i < kIssueIters; ++i) {
+#define PPERM_DEP_GROUP                                  \
+        "v_cmp_gt_u32_e64 %0, %2, %4\n\t"                \
+        "v_cmp_gt_u32_e64 %1, %3, %5\n\t"                \
+        "s_and_b64 %0, %0, exec\n\t"                     \
+        "s_and_b64 %1, %1, exec\n\t"                     \
+        "s_bcnt1_i32_b64 %2, %0\n\t"                     \
+        "s_bcnt1_i32_b64 %3, %1\n\t"                     \
+        "v_add_u32 %4, %2, %4\n\t"                       \
+        "v_add_u32 %5, %3, %5\n\t"
+        asm volatile(PPERM_DEP_GROUP PPERM_DEP_GROUP PPERM_DEP_GROUP PPERM_DEP_GROUP
+                     : "+s"(m0), "+s"(m1), "+s"(s0), "+s"(s1), "+v"(v0), "+v"(v1)
+                     :
+                     : "scc");
+#undef PPERM_DEP_GROUP
+    }
+    const uint32_t x = v0 ^ v1 ^ s0 ^ s1 ^ (uint32_t)m0 ^ (uint32_t)(m1 >> 32);
+    if (x == 0x9E3779B9u) sink[threadIdx.x & 63u] = x;
+}
+
 char g_err[256];
 
 int fail(hipError_t e, const char* what) {
@@ -223,6 +251,19 @@ extern "C" int pperm_probe(void* d_buffer, size_t bytes, void* hip_stream, pperm
     if (rc) return rc;
     out->mixed_ms = ms;
     out->mixed_instr_per_s = issue_waves * kIssueIters * kIssuePerIter / (ms * 1e-3);
+    rc = timed(s, [&] {
+        hipLaunchKernelGGL(dependent_probe_kernel, dim3(ncu * kIssueBlocksPerCU), dim3(256), 0, s, sink, 3u);
+    }, &ms);
+    if (rc) return rc;
+    out->dependent_ms = ms;
+    out->dependent_instr_per_s = issue_waves * kIssueIters * kIssuePerIter / (ms * 1e-3);
+    // the same at half the waves (four per SIMD)
+    rc = timed(s, [&] {
+        hipLaunchKernelGGL(dependent_probe_kernel, dim3(ncu * kIssueBlocksPerCU / 2u), dim3(256), 0, s, sink, 3u);
+    }, &ms);
+    if (rc) return rc;
+    out->dependent4_ms = ms;
+    out->dependent4_instr_per_s = issue_waves / 2.0 * kIssueIters * kIssuePerIter / (ms * 1e-3);
     int clk = 0;
     PROBE_TRY(hipDeviceGetAttribute(&clk, hipDeviceAttributeClockRate, dev));
     out->clock_khz = (uint32_t)clk;

@@ -227,9 +227,9 @@ def run_batch_noalloc(problems, tours_each, stream=None):
 
 def probe(device=None, stream=None):
     """The measured ceilings of the device (pperm_probe): 32-bit VALU lane-ops/s,
-    LDS bytes/s, L2 bytes/s, and wave instructions/s of scalar-only and mixed
-    vector/scalar streams, with the duration of each timed launch, the clock
-    attribute and the SIMD count."""
+    LDS bytes/s, L2 bytes/s, and wave instructions/s of scalar-only, mixed
+    vector/scalar and dependent vector/scalar streams, with the duration of
+    each timed launch, the clock attribute and the SIMD count."""
     lib = _abi.load()
     device = torch.device(device if device is not None else "cuda")
     res = _abi.ProbeResult()

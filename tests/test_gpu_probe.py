@@ -14,9 +14,9 @@ def test_probe_reports_positive_finite_ceilings():
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     assert r["compute_units"] == cus and r["simds"] == 4 * cus
     for f in ("valu_lane_ops_per_s", "lds_bytes_per_s", "l2_bytes_per_s", "salu_instr_per_s",
-              "mixed_instr_per_s"):
+              "mixed_instr_per_s", "dependent_instr_per_s", "dependent4_instr_per_s"):
         assert math.isfinite(r[f]) and r[f] > 0, f
-    for f in ("valu_ms", "lds_ms", "l2_ms", "salu_ms", "mixed_ms"):
+    for f in ("valu_ms", "lds_ms", "l2_ms", "salu_ms", "mixed_ms", "dependent_ms", "dependent4_ms"):
         assert r[f] > 0, f
     assert r["clock_khz"] > 0
     # an issue rate above a few wave instructions per SIMD per cycle would mean
