@@ -103,7 +103,8 @@ typedef struct pperm_seq_stats {
     uint64_t traps;       /* arrivals at a walk with a_+ = 0                         */
     uint64_t tours;       /* passes through the empty walk                           */
     uint64_t max_depth;   /* deepest pending-copy stack                              */
-    uint64_t digest;      /* FNV-1a 64 over one byte per step: dir | a_+ << 3        */
+    uint64_t digest;      /* FNV-1a 32 over one byte per step, dir | a_+ << 3,
+                             zero-extended (instrumentation: compares walks)   */
     uint64_t capped;      /* 1 once the step cap stopped this sequence               */
 } pperm_seq_stats;
 

@@ -367,12 +367,15 @@ typedef struct {
     uint64_t traps;      /* arrivals with a_+ = 0 */
     uint64_t tours;      /* passes through the empty walk */
     uint64_t max_depth;  /* deepest copy stack */
-    uint64_t digest;     /* FNV-1a 64 over one byte per growth: dir | a_+ << 3 */
+    uint64_t digest;     /* FNV-1a 32 over one byte per growth, dir | a_+ << 3, zero-extended */
     uint64_t capped;     /* 1 once the step cap stopped this sequence */
 } orc_seq_stats;
 
-#define ORC_FNV_OFFSET 0xCBF29CE484222325ull
-#define ORC_FNV_PRIME  0x00000100000001B3ull
+/* The trajectory digest is instrumentation for comparing walks, not part of
+ * the method: FNV-1a with 32-bit state (offset basis and prime of its
+ * published definition). */
+#define ORC_FNV_OFFSET 2166136261u
+#define ORC_FNV_PRIME  16777619u
 
 void orc_stats_init(orc_seq_stats* st, int64_t count)
 {
@@ -482,7 +485,7 @@ int orc_run_sequence(const orc_params* P, const orc_xf* G, uint64_t MG,
                 /* Rosenbluth growth (Sec. 1): the j-th free neighbour, W *= a_+ (eqn (2)). */
                 unsigned j = (unsigned)(((uint64_t)B[0] * (uint64_t)a) >> 32);
                 int dir = orc_nth_free(mask, j);
-                st->digest = (st->digest ^ (uint64_t)(dir | (a << 3))) * ORC_FNV_PRIME;
+                st->digest = (uint32_t)(((uint32_t)st->digest ^ (uint32_t)(dir | (a << 3))) * ORC_FNV_PRIME);
                 w = orc_xf_mul(w, (double)a);
                 orc_walk_push(&walk, dir);
                 st->steps += 1;

@@ -258,7 +258,11 @@ __device__ __forceinline__ void wave_fence() {
 enum : int { PH_NEED_SEQ = 0, PH_NEED_TOUR = 1, PH_NEED_BT = 2, PH_AT_NODE = 3, PH_DONE = 4,
              PH_ABORT = 5 };
 
-constexpr uint64_t FNV_PRIME = 0x00000100000001B3ull;
+// Trajectory digest of a sequence (instrumentation, not part of the method):
+// FNV-1a 32 over one byte per growth step, dir | a_+ << 3, kept zero-extended
+// in a 64-bit statistics word.
+constexpr uint32_t FNV_OFFSET = 2166136261u;
+constexpr uint32_t FNV_PRIME = 16777619u;
 
 // Bits 0, DP, 2*DP, ... (W of them): the lanes of one direction in a team.
 template <int DP, int W>
@@ -577,7 +581,7 @@ __global__ void __launch_bounds__(64) run_kernel(RunArgs A) {
                 uint32_t mm = freem;
                 for (uint32_t i = 0; i < j; ++i) mm &= mm - 1u;
                 const int dir = __ffs(mm) - 1;
-                st_digest = (st_digest ^ (uint64_t)((uint32_t)dir | (a << 3))) * FNV_PRIME;
+                st_digest = (uint64_t)(((uint32_t)st_digest ^ ((uint32_t)dir | (a << 3))) * FNV_PRIME);
                 if (my_ins >= 0 && pdir == dir) {
                     table[my_ins] = nk;
                     sid[n + 1] = (uint16_t)my_ins;
@@ -855,7 +859,7 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
     const uint32_t capv = cap ? cap : 0xFFFFFFFFu;   // step cap of this call (0: none)
     uint64_t c_events = 0;                     // events: the sum over tours of k
     uint64_t cv = 0;
-    uint64_t digest = ufirst64(P.stats[(size_t)s * STATS_WORDS + ST_DIGEST]);
+    uint32_t digest = (uint32_t)ufirst64(P.stats[(size_t)s * STATS_WORDS + ST_DIGEST]);
     bool abort = false;
     // the registers of the copy stack (see the tour loop)
     uint32_t cs_n = 0u, cs_rem = 0u;
@@ -931,10 +935,12 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
             // eqn (6): r = W / [W_n], [W_n] = sum / seen (own epoch data weighted
             // N in Algorithm 2), evaluated as (W * seen) / sum; only when a
             // decision is due at this length (not after a resume or at n = 0)
-            XF sum = {0.0, 0};
-            uint32_t ub = 0u, fi = 0u;
-            if (control) {
-                sum = xf_add_nz(Gc, xf_mul_nz(Lc, pool));
+            // (computed on every step and kept only when a decision is due, so
+            // that the scan's first window resolves in the same block and its
+            // scalar work can fill the waits of this chain)
+            const XF sum = xf_add_nz(Gc, xf_mul_nz(Lc, pool));
+            uint32_t ub, fi;
+            {
                 const double r = xf_ratio_nz(xf_mul_nz(w, seen), sum);
                 const double u = lane_value(ul, li);
                 const double f = floor(r);
@@ -946,10 +952,8 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
                 // only keeps the conversion defined); r >= 1 iff fi >= 1.
                 // (Converted in vector registers, then read once.)
                 uint32_t fv = (uint32_t)__builtin_fmin(f, 4294967295.0);
-                asm volatile("" : "+v"(fv));
                 fi = ufirst(fv);
             }
-            asm volatile("" ::"s"(ub), "s"(fi));
 
             // ---- resolve the scan: usually the first window settles every direction ----
             uint64_t freem;                    // directions resolved free
@@ -962,6 +966,16 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
                 freem = ed & ~hd;
                 insm = empm;                   // (only fields of free directions are read)
                 uint64_t pending = F::HI & ~(hd | ed);
+                // scheduling groups for this block (twenty vector instructions,
+                // then scalar and vector ones alternating one to two), which
+                // issue a step's decision and window resolution faster than the
+                // compiler's own order does
+                __builtin_amdgcn_sched_group_barrier(0x002, 20, 0);
+#pragma unroll
+                for (int g = 0; g < 16; ++g) {
+                    __builtin_amdgcn_sched_group_barrier(0x004, 1, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);
+                }
                 uint32_t base = (uint32_t)poff;
                 while (pending != 0u) {
                     // a run longer than the window: read the next W positions
@@ -1040,7 +1054,7 @@ __device__ __forceinline__ uint32_t walk_sequence(const ProblemDesc& P, uint32_t
                         (uint32_t)(freem >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)freem, 0u));
                     const uint64_t pick = __ballot(below == j) & freem;
                     const int dir = (__ffsll((unsigned long long)pick) - 1) >> F::LW;
-                    digest = (digest ^ (uint64_t)((uint32_t)dir | (a << 3))) * FNV_PRIME;
+                    digest = (digest ^ ((uint32_t)dir | (a << 3))) * FNV_PRIME;
                     // insertion slot: the first empty slot of the chosen direction's run
                     const uint32_t il =
                         (uint32_t)__builtin_ctz((uint32_t)(insm >> (dir * W)) & FIELD) + (uint32_t)(dir * W);
@@ -1662,9 +1676,9 @@ __global__ void __launch_bounds__(256) init_state_kernel(uint64_t* stats, uint32
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < words;
          i += (size_t)gridDim.x * 256)
         zero[i] = 0u;
-    // stats rows: counters 0, digest = FNV-1a offset basis
+    // stats rows: counters 0, digest = the FNV-1a 32 offset basis
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (size_t)gridDim.x * 256)
-        stats[i * STATS_WORDS + ST_DIGEST] = 0xCBF29CE484222325ull;
+        stats[i * STATS_WORDS + ST_DIGEST] = FNV_OFFSET;
 }
 
 template <int D, int TS>

@@ -257,6 +257,31 @@ def test_first_tour_is_a_rosenbluth_walk(dim, seed):
     assert a.stats["digest"][0] == b.stats["digest"][0]
 
 
+def _fnv1a32(data):
+    # FNV-1a with 32-bit state, from its published definition
+    h = 0x811C9DC5
+    for b in data:
+        h = ((h ^ b) * 0x01000193) & 0xFFFFFFFF
+    return h
+
+
+@pytest.mark.parametrize("dim,seed,tours", [(2, 3, 1), (2, 5, 2), (3, 7, 3)])
+def test_trajectory_digest_is_fnv1a_32_of_the_steps(dim, seed, tours):
+    # The published test vector pins the constants; with n_max = 1 every tour is
+    # one growth from the origin (no decision is due at n = 0), whose byte is
+    # dir | a_+ << 3 with a_+ = 2d, so the digest is FNV-1a 32 of one such byte
+    # per tour, for some sequence of directions.
+    assert _fnv1a32(b"") == 0x811C9DC5 and _fnv1a32(b"a") == 0xE40C292C
+    o = oracle.Oracle(dim, 1, 1, seed)
+    o.run_tours(tours)
+    assert int(o.stats["steps"][0]) == tours
+    import itertools
+    byte = lambda d: d | ((2 * dim) << 3)
+    candidates = {_fnv1a32(bytes(byte(d) for d in dirs))
+                  for dirs in itertools.product(range(2 * dim), repeat=tours)}
+    assert int(o.stats["digest"][0]) in candidates
+
+
 @pytest.mark.parametrize("dim,n_max,seed,tours", [(2, 20, 1, 3000), (2, 40, 2, 2000), (3, 30, 3, 2000)])
 def test_iterative_matches_recursive_description(dim, n_max, seed, tours):
     o = oracle.Oracle(dim, n_max, 1, seed)
