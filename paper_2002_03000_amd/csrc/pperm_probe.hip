@@ -1,7 +1,9 @@
 // Microbenchmarks of the ceilings the growth kernel is reported against
 // (include/pperm_probe.h): 32-bit VALU issue, LDS read bandwidth and L2 read
-// bandwidth, and the instruction issue rate of a SIMD for a scalar-only and a
-// mixed vector/scalar stream, each measured on the whole device with HIP events.
+// bandwidth, and the instruction issue rate of a SIMD for scalar-only streams,
+// for independent vector and scalar instructions alternating, and for vector
+// and scalar instructions that feed each other, each measured on the whole
+// device with HIP events.
 //
 // Every probe fills the device (workgroups per CU sized for its resource) and
 // keeps its result live with a store that never happens in practice (the
